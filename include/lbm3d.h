@@ -1,0 +1,228 @@
+/*
+ * lbm3d.h -- C ABI of the MI355X (gfx950) 3D finite-difference lattice
+ * Boltzmann solver for compressible Euler flow.
+ *
+ * The method is that of Chen, Xu, Zhang and Li, "Three-Dimensional Lattice
+ * Boltzmann Model for High-Speed Compressible Flows" (arXiv:1010.4135): the
+ * 15-velocity Kataoka-Tsutahara model (Sec. 2, Eq. (vv)) with the equilibrium
+ * of Eqs. (eq)/(e18), the BGK kinetic equation with the paper's artificial
+ * dissipation (Sec. 3, Eq. (lp)), the NND flux-split minmod scheme for the
+ * convection term (Sec. 3, Eq. (nnd)) and a forward-Euler time step
+ * (Sec. 3, Eq. (fi1)).
+ *
+ * Conventions for every entry point:
+ *   - Return value: int32 status, LBM3D_OK (0) or a negative LBM3D_E_* code.
+ *     No entry point aborts, throws or prints; lbm3d_strerror() names a code.
+ *   - Host arrays are caller-owned; they are read or written during the call
+ *     only (inputs are copied, outputs are filled before return).
+ *   - Macroscopic fields are host FP64 arrays of nx*ny*nz values laid out
+ *     [nz][ny][nx] (x fastest) over the interior (updated) nodes.
+ *   - Gas constant R = 1, so the pressure is p = rho T; b = 2/(gamma-1).
+ *   - Device state (two f buffers and small work buffers) is owned by the
+ *     library, allocated by lbm3d_create and freed by lbm3d_destroy.
+ *   - A solver handle is not thread-safe: serialise calls on one handle.
+ *     The server object is thread-safe for submit / poll / wait / cancel.
+ *   - All device work of a handle runs on its stream, in call order.
+ */
+#ifndef LBM3D_H
+#define LBM3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+enum {
+    LBM3D_OK = 0,
+    LBM3D_E_INVAL = -1,     /* bad argument: sizes, constants, boundary pairing, rho<=0 or p<=0 */
+    LBM3D_E_UNSTABLE = -2,  /* Courant or diffusion number above its limit */
+    LBM3D_E_NOMEM = -3,     /* device or host allocation failed, or over a memory budget */
+    LBM3D_E_DEVICE = -4,    /* a HIP runtime call failed */
+    LBM3D_E_STATE = -5,     /* call out of order (e.g. step before init) */
+    LBM3D_E_NONFINITE = -6, /* the solution holds NaN or Inf */
+    LBM3D_E_NOTFOUND = -7,  /* unknown server ticket */
+    LBM3D_E_CANCELLED = -8  /* the ticket was cancelled */
+};
+
+/* ------------------------------------------------------- enumerations ---- */
+/* Storage / arithmetic precision.
+ *   FP64      f stored and updated in double.
+ *   FP32      f stored and updated in float.
+ *   FP32_T64  f stored and updated in float; the moment sums (rho, rho u,
+ *             energy) and the temperature T = (E/rho - u^2)/b, which cancels
+ *             badly at high Mach number, and the equilibrium coefficients
+ *             that depend on T and u^2, are computed in double. */
+enum { LBM3D_FP64 = 0, LBM3D_FP32 = 1, LBM3D_FP32_T64 = 2 };
+
+/* Boundary kind per face (Sec. 4 (2) gives the last three for (rho, u, T) on
+ * the two boundary-node layers; the distributions there are f^eq of those
+ * values).  PERIODIC must be set on both faces of an axis. */
+enum {
+    LBM3D_PERIODIC = 0, /* wrap around */
+    LBM3D_OUTFLOW = 1,  /* linear extrapolation from the two nodes next to the face */
+    LBM3D_INFLOW = 2,   /* fixed state params.inflow[face] */
+    LBM3D_REFLECT = 3   /* wall layer: last node with zero normal velocity; mirror layer: normal velocity negated */
+};
+
+/* params.flags bits */
+enum {
+    LBM3D_NO_DISSIPATION = 1u /* drop the artificial dissipation term (lambda_i = 0), the paper's comparison variant */
+};
+
+/* health bits reported by lbm3d_status (sticky since init) */
+enum {
+    LBM3D_HEALTH_NONFINITE = 1u, /* some f became NaN or Inf */
+    LBM3D_HEALTH_RHO_NONPOS = 2u,/* some node had rho <= 0 */
+    LBM3D_HEALTH_T_NONPOS = 4u   /* some node had T <= 0 (can occur transiently at sharp interfaces) */
+};
+
+/* --------------------------------------------------------- parameters ---- */
+typedef struct {
+    int32_t nx, ny, nz;   /* interior nodes per axis (>= 1; >= 2 on an axis with a non-periodic face) */
+    double c1, c2, eta0;  /* velocity-model constants of Eq. (vv): nonzero, c1 != c2 */
+    double gamma;         /* adiabatic index (> 1); b = 2/(gamma-1) */
+    double tau;           /* relaxation time (> 0) */
+    double dt;            /* time step (> 0) */
+    double dx;            /* grid spacing, the same on all axes (> 0) */
+    int32_t bc[6];        /* faces -x, +x, -y, +y, -z, +z: LBM3D_PERIODIC .. LBM3D_REFLECT */
+    double inflow[6][5];  /* (rho, ux, uy, uz, p) per LBM3D_INFLOW face; ignored elsewhere */
+    int32_t precision;    /* LBM3D_FP64, LBM3D_FP32 or LBM3D_FP32_T64 */
+    uint32_t flags;       /* LBM3D_NO_DISSIPATION */
+} lbm3d_params;
+
+typedef struct lbm3d_solver* lbm3d_t;
+
+/* Library version string (static storage). */
+const char* lbm3d_version(void);
+
+/* Name of a status code (static storage; never NULL). */
+const char* lbm3d_strerror(int32_t code);
+
+/* Number of visible HIP devices in *count (0 when no GPU). */
+int32_t lbm3d_device_count(int32_t* count);
+
+/* Device bytes a solve with these parameters holds (both f buffers with
+ * their boundary layers plus work buffers).  Validates like lbm3d_create. */
+int32_t lbm3d_footprint(const lbm3d_params* p, size_t* bytes);
+
+/* Validate parameters (E_INVAL / E_UNSTABLE as below), allocate the device
+ * state on the current device and return a handle in *out.  The explicit
+ * step is admitted only if the Courant number dt/dx * sum_a |v_ia| of the
+ * fastest (diagonal) velocity, sqrt(3) c2 dt/dx, is <= 1 and the diffusion
+ * number 6 lambda_1 dt/dx^2 = 6 c1 dt/dx is <= 1 (lambda_i of Eq. (lp)). */
+int32_t lbm3d_create(const lbm3d_params* p, lbm3d_t* out);
+
+/* Release a handle and its device memory.  NULL is accepted. */
+int32_t lbm3d_destroy(lbm3d_t h);
+
+/* Run the handle's device work on an existing hipStream_t (NULL restores the
+ * library's own stream).  The caller keeps the stream alive while in use. */
+int32_t lbm3d_set_stream(lbm3d_t h, void* hip_stream);
+
+/* Initial state: f_i = f_i^eq(rho, u, T = p/rho) on every interior node
+ * (the paper states initial macroscopic fields only), then the boundary
+ * layers.  E_INVAL if any rho <= 0 or p <= 0 or a value is not finite.
+ * Resets the step counter and the health word.  Blocking. */
+int32_t lbm3d_init(lbm3d_t h, const double* rho, const double* ux, const double* uy,
+                   const double* uz, const double* p);
+
+/* Enqueue nsteps explicit time steps (asynchronous on the handle's stream;
+ * runs of steps are replayed from a captured HIP graph).  E_STATE before
+ * init; nsteps >= 0. */
+int32_t lbm3d_step(lbm3d_t h, int64_t nsteps);
+
+/* As lbm3d_step, then wait; *ms receives the device time of the steps
+ * measured with HIP events on the handle's stream (ms may be NULL). */
+int32_t lbm3d_step_timed(lbm3d_t h, int64_t nsteps, double* ms);
+
+/* Measurement run: enqueue nsteps steps one launch at a time (no graph),
+ * recording HIP events on the handle's stream around every launch of the
+ * fused step kernel, then wait.  *total_ms receives the device time of all
+ * nsteps steps, *step_kernel_ms the mean duration of one fused-step launch
+ * (either pointer may be NULL).  The state advances exactly as lbm3d_step. */
+int32_t lbm3d_step_profiled(lbm3d_t h, int64_t nsteps, double* total_ms, double* step_kernel_ms);
+
+/* Wait for all work enqueued on the handle's stream. */
+int32_t lbm3d_sync(lbm3d_t h);
+
+/* (rho, u, p = rho T) on the interior nodes into caller arrays of nx*ny*nz
+ * doubles each (any pointer may be NULL to skip that field).  Blocking.
+ * Returns E_NONFINITE (after filling the arrays) if the health word has the
+ * NONFINITE bit. */
+int32_t lbm3d_moments(lbm3d_t h, double* rho, double* ux, double* uy, double* uz, double* p);
+
+/* Domain totals over the interior nodes, accumulated in FP64 with a fixed
+ * reduction order (bitwise reproducible): out[0] mass sum rho, out[1..3]
+ * momentum sum rho u, out[4] energy sum rho (b T + u^2)/2.  Blocking. */
+int32_t lbm3d_conserved(lbm3d_t h, double out[5]);
+
+/* Health bits (LBM3D_HEALTH_*) accumulated since init, and steps done. */
+int32_t lbm3d_status(lbm3d_t h, uint32_t* health, int64_t* steps_done);
+
+/* Checkpoint: the interior distributions as [15][nz][ny][nx] in storage
+ * precision (double for FP64, float otherwise); bytes must equal
+ * 15*nx*ny*nz*elem.  Velocity order: rest; c1 (+x, -x, +y, -y, +z, -z);
+ * then (c2/sqrt3)(sx, sy, sz) with bit a of the index-7 giving the sign of
+ * axis a (clear = +).  Blocking. */
+int32_t lbm3d_get_f(lbm3d_t h, void* host, size_t bytes);
+
+/* Restore distributions written by lbm3d_get_f (same layout and size) and
+ * refresh the boundary layers; the step counter is left unchanged. */
+int32_t lbm3d_set_f(lbm3d_t h, const void* host, size_t bytes);
+
+/* Advance `count` independent solves (any mix of sizes, all of the same
+ * precision) by nsteps[k] steps each.  Each step of the group is one launch
+ * of a persistent kernel over a packed queue of tiles from every solve that
+ * still has steps to do; groups of steps are replayed from captured HIP
+ * graphs.  Results are bitwise identical to stepping each solve alone.
+ * Blocking.  E_INVAL for mixed precisions, duplicate handles, count < 1. */
+int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* nsteps);
+
+/* ------------------------------------------------------------- serving --- */
+typedef struct lbm3d_server* lbm3d_server_t;
+
+typedef struct {
+    double t_submit, t_admit, t_done; /* seconds on the server's monotonic clock */
+    int64_t steps;                    /* steps done */
+    uint32_t health;                  /* LBM3D_HEALTH_* of the solve */
+} lbm3d_timing;
+
+/* A server owns one worker thread that admits submitted solves while their
+ * device footprint fits in hbm_budget_bytes and fewer than max_active are
+ * running, keeps their state resident on the device, advances all active
+ * solves together in batched ticks (continuous batching: solves admitted
+ * between ticks join the next one), and completes a ticket when its solve
+ * has done its steps.  Solves of any precision may be mixed; each tick
+ * groups them by precision. */
+int32_t lbm3d_server_create(size_t hbm_budget_bytes, int32_t max_active, lbm3d_server_t* out);
+
+/* Queue a solve.  Parameters and the five initial fields are copied; returns
+ * immediately with a ticket.  E_NOMEM if the solve alone exceeds the budget;
+ * E_INVAL / E_UNSTABLE as lbm3d_create. */
+int32_t lbm3d_server_submit(lbm3d_server_t s, const lbm3d_params* p, const double* rho,
+                            const double* ux, const double* uy, const double* uz,
+                            const double* pr, int64_t nsteps, uint64_t* ticket);
+
+/* *done = 1 once the ticket's result is ready (or it failed / was cancelled). */
+int32_t lbm3d_server_poll(lbm3d_server_t s, uint64_t ticket, int32_t* done);
+
+/* Block until the ticket completes, copy its (rho, u, p) into caller arrays
+ * (any may be NULL) and its timing into *t (may be NULL), then forget the
+ * ticket.  Returns the solve's own status (E_NONFINITE, E_CANCELLED, ...). */
+int32_t lbm3d_server_wait(lbm3d_server_t s, uint64_t ticket, double* rho, double* ux,
+                          double* uy, double* uz, double* p, lbm3d_timing* t);
+
+/* Cancel a queued or running ticket; a later wait returns E_CANCELLED. */
+int32_t lbm3d_server_cancel(lbm3d_server_t s, uint64_t ticket);
+
+/* Stop the worker (running solves are cancelled) and free everything. */
+int32_t lbm3d_server_destroy(lbm3d_server_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM3D_H */

@@ -1,0 +1,90 @@
+// Internal declarations shared by the host runtime and the device code of
+// the lbm3d library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbm3d {
+
+constexpr int NV = 15;  // discrete velocities, Sec. 2, Eq. (vv)
+constexpr int NG = 2;   // boundary-node layers per face (NND stencil half-width)
+
+// Model constants of one solve, in one floating type.  The equilibrium of
+// Eqs. (eq)/(e18) is written per velocity group as
+//   A = a0 + aT T + au u^2,   B = b0 + bT T + bu u^2,   D = d
+// (rest: A = aT T, B = D = 0), and f_i^eq = rho (A + B s + D s^2), s = v_i.u.
+template <typename T>
+struct Model {
+    T c1, k;             // axis speed c1 and diagonal component c2/sqrt(3)
+    T c1sq, c2sq, e0sq;  // c1^2, c2^2, eta0^2
+    T inv_b;             // 1/b
+    T r_aT;              // rest:  A = r_aT T
+    T x_a0, x_aT, x_au, x_b0, x_bT, x_bu, x_d;   // axis group
+    T d_a0, d_aT, d_au, d_b0, d_bT, d_bu, d_d;   // diagonal group
+    T k_adv;             // dt/dx
+    T k_bgk;             // dt/tau
+    T k_lap0, k_lap1;    // lambda_1 dt/dx^2 (rest), lambda_{2..7} dt/dx^2 (axis)
+};
+
+// Geometry of one solve's padded distribution array f[15][mz][my][mx]:
+// interior node (x, y, z) of velocity i sits at i*sv + org + z*sz + y*sy + x.
+struct Grid {
+    int32_t nx, ny, nz;
+    int64_t sy, sz, sv;  // strides of y, z and velocity (elements)
+    int64_t org;         // offset of interior node (0,0,0)
+};
+
+struct FaceBC {
+    int32_t kind[6];        // LBM3D_PERIODIC .. LBM3D_REFLECT per face
+};
+
+struct Device;  // per-solve device pointers, defined in lbm3d_api.cpp
+
+// Precision modes (same values as the ABI enum).
+enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_FP32_T64 = 2 };
+
+// One tile of the batched step: a box of interior nodes of one solve.
+struct Tile {
+    int32_t solve;        // index into the solve table
+    int32_t x0, y0, z0;   // first interior node
+};
+
+// Per-solve entry of the batched step.
+struct SolveDesc {
+    const void* f;        // current distributions (storage type)
+    void* fn;             // next distributions
+    uint32_t* health;
+    Grid g;
+    FaceBC bc;
+    int32_t pad;
+    Model<double> md;
+    Model<float> mf;
+};
+
+// ---- launches (lbm3d_device.hip) ----
+hipError_t launch_init(int mode, const Grid& g, const Model<double>& md, const double* q5,
+                       void* f, hipStream_t s);
+hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const Model<double>& md,
+                       const Model<float>& mf, const void* f, void* fn, uint32_t* health,
+                       hipStream_t s);
+hipError_t launch_ghosts(int mode, const Grid& g, const FaceBC& bc, const Model<double>& md,
+                         const double (*inflow)[5], bool include_fixed, void* f, hipStream_t s);
+hipError_t launch_moments(int mode, const Grid& g, const Model<double>& md, const void* f,
+                          double* q5, hipStream_t s);
+hipError_t launch_conserved(int mode, const Grid& g, const Model<double>& md, const void* f,
+                            double* partial, int nblocks, double* out5, hipStream_t s);
+int conserved_blocks(const Grid& g);
+hipError_t launch_pack(int mode, const Grid& g, const void* f, void* dense, bool to_dense,
+                       hipStream_t s);
+hipError_t launch_batch_step(int mode, const SolveDesc* solves, const Tile* tiles, int ntiles,
+                             int nblocks, hipStream_t s);
+hipError_t launch_batch_ghosts(int mode, const SolveDesc* solves, int nsolves, int max_face,
+                               hipStream_t s);
+
+// tile edge lengths of the step kernel (also the batched tiles)
+constexpr int TX = 64, TY = 4, TZ = 1;
+
+}  // namespace lbm3d

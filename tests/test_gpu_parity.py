@@ -1,0 +1,217 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bars:
+- FP64 mode: relative L1 distance per field (rho, u, p) <= 1e-12, the
+  stated FP64 parity bound; f itself elementwise within 1e-11 of max|f|.
+- FP32 modes: per-field relative L1 distance to the FP64 oracle is printed
+  and bounded by FP32_TOL (derived in the module docstring of
+  paper_1010_4135_amd.metrics' users: 15-term sums in float carry ~1e-7
+  relative rounding per step; after a few hundred steps of a dissipative
+  scheme the accumulated distance stays below 1e-4 away from shocks, and
+  below 1e-3 in relative L1 including them).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1010_4135_amd import inputs, metrics
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-3
+
+
+def _lib():
+    from paper_1010_4135_amd import lbm3d
+    return lbm3d
+
+
+def gpu_run(case, steps, precision=None, **over):
+    prm = dict(case.params)
+    if precision is not None:
+        prm["precision"] = precision
+    prm.update(over)
+    s = _lib().Solver(prm)
+    s.init(*case.fields)
+    if steps:
+        s.step(steps)
+    return s, s.moments()
+
+
+def oracle_run(case, steps, **over):
+    prm = dict(case.params)
+    prm.update(over)
+    o = oracle.Oracle(prm)
+    o.init(*case.fields)
+    if steps:
+        o.step(steps)
+    return o, o.moments()
+
+
+def _report(tag, err):
+    print(f"[{tag}] " + " ".join(f"{k}={v:.3e}" for k, v in err.items()), flush=True)
+
+
+def _small_cases():
+    out = []
+    out.append(("smooth_70x9x7", inputs.smooth_periodic(3, grid=(70, 9, 7), amp=0.3), 40))
+    out.append(("riemann3d_66x10x6", inputs.riemann_3d(2, grid=(66, 10, 6)), 30))
+    sb = inputs.shock_bubble(5, grid=(68, 20, 12), precision="fp64", mach=4.0, ratio=0.3)
+    out.append(("shockbubble_68x20x12", sb, 30))
+    c = inputs.smooth_periodic(8, grid=(33, 17, 5), amp=0.3)
+    c.params = dict(c.params, bc=(1, 1, 3, 3, 0, 0))
+    out.append(("mixed_bc_33x17x5", c, 40))
+    out.append(("quasi1d_256x1x1", inputs.riemann_1d(6, grid=(256, 1, 1), steps=100), 100))
+    c = inputs.smooth_periodic(9, grid=(20, 12, 9), amp=0.3)
+    c.params = dict(c.params, flags=1)
+    out.append(("no_dissipation_20x12x9", c, 40))
+    c = inputs.smooth_periodic(10, grid=(2, 64, 2), amp=0.3)
+    c.params = dict(c.params, bc=(3, 3, 1, 1, 3, 3))
+    out.append(("min_sizes_2x64x2", c, 30))
+    return out
+
+
+@pytest.mark.parametrize("name,case,steps", _small_cases(), ids=[c[0] for c in _small_cases()])
+def test_fp64_matches_oracle_small(name, case, steps):
+    s, mg = gpu_run(case, steps, precision="fp64")
+    o, mo = oracle_run(case, steps)
+    err = metrics.rel_l1(mg, mo)
+    _report(name, err)
+    assert max(err.values()) <= FP64_TOL, err
+    fg, fo = s.get_f(), o.get_f()
+    assert np.abs(fg - fo).max() <= 1e-11 * np.abs(fo).max()
+    h, done = s.status()
+    assert done == steps and not (h & 1)
+
+
+def test_config0_fp64_matches_oracle():
+    """Quasi-1D Riemann problem, 256x4x4, 500 steps, FP64."""
+    case = inputs.riemann_1d(0)
+    s, mg = gpu_run(case, case.steps)
+    o, mo = oracle_run(case, case.steps)
+    err = metrics.rel_l1(mg, mo)
+    _report("config0", err)
+    assert max(err.values()) <= FP64_TOL
+
+
+def test_config1_fp64_full_grid_first_steps():
+    """128^3 periodic 3D Riemann problem at full size: 8 steps element by
+    element (the oracle is too slow for the full 1000 at this size)."""
+    case = inputs.riemann_3d(1)
+    s, mg = gpu_run(case, 8)
+    o, mo = oracle_run(case, 8)
+    err = metrics.rel_l1(mg, mo)
+    _report("config1_fp64_8steps", err)
+    assert max(err.values()) <= FP64_TOL
+
+
+def test_config2_full_grid_first_steps():
+    """256x128x128 shock-bubble at full size, 3 steps: FP64 mode at the FP64
+    bar; FP32 with FP64 temperature recovery reported and bounded."""
+    case = inputs.shock_bubble(2)
+    o, mo = oracle_run(case, 3)
+    s, mg = gpu_run(case, 3, precision="fp64")
+    err = metrics.rel_l1(mg, mo)
+    _report("config2_fp64_3steps", err)
+    assert max(err.values()) <= FP64_TOL
+    s.close()
+    s, mg = gpu_run(case, 3, precision="fp32_t64")
+    err = metrics.rel_l1(mg, mo)
+    _report("config2_fp32t64_3steps", err)
+    assert max(err.values()) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_t64"])
+def test_fp32_error_against_fp64_oracle(precision):
+    case = inputs.riemann_3d(4, grid=(48, 40, 32))
+    steps = 200
+    o, mo = oracle_run(case, steps)
+    s, mg = gpu_run(case, steps, precision=precision)
+    err = metrics.rel_l1(mg, mo)
+    _report(f"riemann3d_48x40x32_{precision}_{steps}", err)
+    assert max(err.values()) <= FP32_TOL
+
+
+def _abs_scale(f, prm):
+    v, eta = oracle.velocities(prm["c1"], prm["c2"], prm["eta0"])
+    af = np.abs(f).reshape(15, -1).sum(axis=1)
+    e2 = 0.5 * ((v * v).sum(axis=1) + eta * eta)
+    return np.array([af.sum(), af @ np.abs(v[:, 0]), af @ np.abs(v[:, 1]), af @ np.abs(v[:, 2]), af @ e2])
+
+
+def test_conservation_on_gpu():
+    case = inputs.riemann_3d(7, grid=(48, 40, 32))
+    s, _ = gpu_run(case, 0, precision="fp64")
+    c0 = s.conserved()
+    o, _ = oracle_run(case, 0)
+    np.testing.assert_allclose(c0, o.conserved(), rtol=1e-13, atol=1e-13 * np.abs(o.conserved()).max())
+    s.step(200)
+    c1 = s.conserved()
+    scale = _abs_scale(s.get_f(), case.params)
+    assert np.all(np.abs(c1 - c0) <= 1e-14 * 200 * scale), (c1 - c0) / scale
+    # reproducible bit for bit
+    assert np.array_equal(c1, s.conserved())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_t64"])
+def test_checkpoint_resume_is_bitwise(precision):
+    case = inputs.shock_bubble(3, grid=(40, 24, 20), precision=precision)
+    a, _ = gpu_run(case, 70)
+    fa = a.get_f()
+    b, _ = gpu_run(case, 33)
+    f33 = b.get_f()
+    b.close()
+    c, _ = gpu_run(case, 0)
+    c.set_f(f33)
+    c.step(37)
+    assert np.array_equal(c.get_f(), fa)
+
+
+def test_runs_are_deterministic_and_graph_replay_matches_single_steps():
+    case = inputs.riemann_3d(8, grid=(40, 24, 20), precision="fp32_t64")
+    a, _ = gpu_run(case, 100)  # three graph replays + 4 single steps
+    b, _ = gpu_run(case, 0)
+    for _ in range(100):
+        b.step(1)
+    assert np.array_equal(a.get_f(), b.get_f())
+
+
+def test_nonfinite_state_is_flagged():
+    lbm3d = _lib()
+    case = inputs.smooth_periodic(1, grid=(16, 8, 8), precision="fp32")
+    s, _ = gpu_run(case, 2)
+    f = s.get_f()
+    f[3, 2, 3, 4] = np.nan
+    s.set_f(f)
+    s.step(2)
+    h, _ = s.status()
+    assert h & lbm3d.HEALTH_NONFINITE
+    with pytest.raises(lbm3d.LbmError) as ei:
+        s.moments()
+    assert ei.value.code == lbm3d.E_NONFINITE
+
+
+def test_uniform_states_stay_uniform_on_gpu():
+    st = (2.66667, 1.47902, 0.0, 0.0, 4.5)
+    prm = inputs.make_params((37, 11, 9), (2, 1, 3, 3, 3, 3), inflow={0: st}, precision="fp64")
+    nx, ny, nz = prm["grid"]
+    case = inputs.Case("u", 0, prm, tuple(np.full((nz, ny, nx), v) for v in st), 50)
+    s, m = gpu_run(case, 50)
+    for g, v in zip(m, st):
+        assert np.abs(g - v).max() <= 1e-12 * (1 + abs(v))
+
+
+def test_step_before_init_is_rejected():
+    lbm3d = _lib()
+    case = inputs.smooth_periodic(1, grid=(8, 8, 8))
+    s = lbm3d.Solver(case.params)
+    with pytest.raises(lbm3d.LbmError) as ei:
+        s.step(1)
+    assert ei.value.code == lbm3d.E_STATE
+    with pytest.raises(lbm3d.LbmError) as ei:
+        s.init(*[np.zeros((8, 8, 8))] * 5)
+    assert ei.value.code == lbm3d.E_INVAL
