@@ -145,6 +145,13 @@ int32_t lbm3d_step_timed(lbm3d_t h, int64_t nsteps, double* ms);
  * (either pointer may be NULL).  The state advances exactly as lbm3d_step. */
 int32_t lbm3d_step_profiled(lbm3d_t h, int64_t nsteps, double* total_ms, double* step_kernel_ms);
 
+/* Launch shape of the fused step kernel: a tile is 64 x `by` nodes in x-y
+ * and `tz` nodes deep in z (by = 2, 4 or 8 -- 8 in the FP32 modes only --
+ * or 0 for the untiled one-node-per-thread kernel; tz >= 1).  Results are
+ * bitwise independent of the shape.  E_INVAL for an unsupported shape. */
+int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz);
+int32_t lbm3d_get_tile(lbm3d_t h, int32_t* by, int32_t* tz);
+
 /* Wait for all work enqueued on the handle's stream. */
 int32_t lbm3d_sync(lbm3d_t h);
 

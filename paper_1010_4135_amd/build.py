@@ -16,6 +16,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # contract a*b+c only within one expression, so that the same source
+    # rounds the same way in every kernel it is inlined into
+    "-ffp-contract=on",
 ]
 
 
@@ -23,7 +26,7 @@ def _objects(jobs):
     objs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
-        obj = os.path.join(CSRC, "_build", src + ".o")
+        obj = os.path.join(CSRC, "_build", "%08x" % (hash(tuple(FLAGS)) & 0xffffffff), src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
         lang = [] if src.endswith(".hip") else ["-x", "hip"]
         cmd = [os.path.join(ROCM, "bin", "hipcc")] + lang + FLAGS + ["-c", path, "-o", obj]
@@ -32,18 +35,30 @@ def _objects(jobs):
     return objs
 
 
-def build() -> str:
+def build(defines=(), out=None) -> str:
+    """Compile and link the library; `defines` are extra -D tuning knobs and
+    `out` an alternative output path (both for tuning builds)."""
+    global FLAGS
+    base_flags = FLAGS
+    FLAGS = FLAGS + ["-D" + d for d in defines]
+    try:
+        return _build(out or LIB)
+    finally:
+        FLAGS = base_flags
+
+
+def _build(lib) -> str:
     jobs = []
     objs = _objects(jobs)
     rc = [j.wait() for j in jobs]
     if any(rc):
         raise RuntimeError("hipcc failed")
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [os.path.join(ROCM, "bin", "hipcc"), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
         "-Wl,-rpath," + os.path.join(ROCM, "lib")]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -29,6 +29,12 @@ int32_t validate(const lbm3d_params* p)
         if (lo != LBM3D_PERIODIC && n[a] < 2) return LBM3D_E_INVAL;
     }
     if (p->nz > 65535) return LBM3D_E_INVAL;
+    {
+        // one velocity plane (with boundary layers and padding) must be
+        // addressable with 32-bit element offsets
+        const double plane = (double)(p->nx + 64 + NG) * (p->ny + 2 * NG) * (p->nz + 2 * NG);
+        if (plane > 2.0e9) return LBM3D_E_INVAL;
+    }
     if (!finite_pos(p->c1) || !finite_pos(p->c2) || !finite_pos(p->eta0)) return LBM3D_E_INVAL;
     if (p->c1 == p->c2) return LBM3D_E_INVAL;  // A_i and B_i divide by c1^2 - c2^2
     if (!std::isfinite(p->gamma) || !(p->gamma > 1.0)) return LBM3D_E_INVAL;
@@ -123,9 +129,12 @@ Grid make_grid(const lbm3d_params* p)
     // velocity planes are separated by an odd number of 256-byte blocks so
     // that the 15 streams do not start on the same memory channel
     const int64_t blk = 256 / (int64_t)elem_size(p->precision);
-    int64_t sv = (g.sz * mz + blk - 1) / blk;
+    // one spare element past the plane: the sink of the step kernel's
+    // stores from lanes outside the grid
+    int64_t sv = (g.sz * mz + 1 + blk - 1) / blk;
     if ((sv & 1) == 0) sv += 1;
     g.sv = sv * blk;
+    g.sink = g.sz * mz;
     g.org = NG * g.sz + NG * g.sy + ox;
     return g;
 }
@@ -176,6 +185,7 @@ int32_t solver_create(const lbm3d_params* p, lbm3d_solver** out)
     h->md = make_model(p);
     h->mf = model_to_float(h->md);
     for (int f = 0; f < 6; f++) h->bc.kind[f] = p->bc[f];
+    h->tile = default_tile(h->mode, h->g);
     h->n = (int64_t)p->nx * p->ny * p->nz;
     const size_t fb = f_bytes(h->g, h->mode);
     h->nred = conserved_blocks(h->g);
@@ -213,9 +223,11 @@ int32_t solver_create(const lbm3d_params* p, lbm3d_solver** out)
 // boundary layers of the new level.
 static hipError_t enqueue_one(lbm3d_solver* h, int cur, hipStream_t s)
 {
-    hipError_t e = launch_step(h->mode, h->g, h->bc, h->md, h->mf, h->f[cur], h->f[cur ^ 1], h->health, s);
+    hipError_t e = launch_step(h->mode, h->g, h->bc, h->tile, h->md, h->mf, h->f[cur], h->f[cur ^ 1], h->health, s);
     if (e != hipSuccess) return e;
-    return launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[cur ^ 1], s);
+    const uint32_t rest = ghost_faces(h->bc, fused_faces(h->g, h->bc, h->tile));
+    if (!rest) return hipSuccess;
+    return launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[cur ^ 1], s, rest);
 }
 
 int32_t solver_enqueue_steps(lbm3d_solver* h, int64_t nsteps)
@@ -379,10 +391,11 @@ int32_t lbm3d_step_profiled(lbm3d_t h, int64_t nsteps, double* total_ms, double*
         const int c = h->cur;
         e = hipEventRecord(ev[2 * k], s);
         if (e == hipSuccess)
-            e = launch_step(h->mode, h->g, h->bc, h->md, h->mf, h->f[c], h->f[c ^ 1], h->health, s);
+            e = launch_step(h->mode, h->g, h->bc, h->tile, h->md, h->mf, h->f[c], h->f[c ^ 1], h->health, s);
         if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], s);
-        if (e == hipSuccess)
-            e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[c ^ 1], s);
+        const uint32_t rest = ghost_faces(h->bc, fused_faces(h->g, h->bc, h->tile));
+        if (e == hipSuccess && rest)
+            e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[c ^ 1], s, rest);
         if (e == hipSuccess) {
             h->cur ^= 1;
             h->steps++;
@@ -402,6 +415,31 @@ int32_t lbm3d_step_profiled(lbm3d_t h, int64_t nsteps, double* total_ms, double*
     if (e != hipSuccess) return dev_err(e);
     if (total_ms) *total_ms = (double)t;
     if (step_kernel_ms) *step_kernel_ms = ksum / (double)nsteps;
+    return LBM3D_OK;
+}
+
+int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz)
+{
+    if (!h) return LBM3D_E_INVAL;
+    TileCfg t;
+    t.by = by;
+    t.tz = tz;
+    if (!tile_supported(h->mode, t)) return LBM3D_E_INVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 2; k++)
+        if (h->graph_exec[k]) {
+            (void)hipGraphExecDestroy(h->graph_exec[k]);
+            h->graph_exec[k] = nullptr;
+        }
+    h->tile = t;
+    return LBM3D_OK;
+}
+
+int32_t lbm3d_get_tile(lbm3d_t h, int32_t* by, int32_t* tz)
+{
+    if (!h) return LBM3D_E_INVAL;
+    if (by) *by = h->tile.by;
+    if (tz) *tz = h->tile.tz;
     return LBM3D_OK;
 }
 

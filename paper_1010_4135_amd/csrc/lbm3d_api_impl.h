@@ -10,6 +10,7 @@ struct lbm3d_solver {
     int mode = 0;
     lbm3d::Grid g{};
     lbm3d::FaceBC bc{};
+    lbm3d::TileCfg tile{};
     lbm3d::Model<double> md{};
     lbm3d::Model<float> mf{};
     int64_t n = 0;             // interior nodes

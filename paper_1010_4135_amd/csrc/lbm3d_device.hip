@@ -1,60 +1,11 @@
 // Device kernels of the lbm3d library for gfx950: initial state, the fused
 // time step, boundary layers, moments, FP64 conservation totals and the
 // checkpoint pack/unpack.
-#include "lbm3d_model.h"
+#include "lbm3d_tile.h"
 
 #include <cmath>
 
 namespace lbm3d {
-
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_INFLOW = 2, BC_REFLECT = 3 };
-enum { H_NONFINITE = 1u, H_RHO = 2u, H_T = 4u };
-
-// ----------------------------------------------------------------- types --
-template <int MODE> struct Types;
-template <> struct Types<MODE_FP64>     { using S = double; using C = double; using M = double; };
-template <> struct Types<MODE_FP32>     { using S = float;  using C = float;  using M = float;  };
-template <> struct Types<MODE_FP32_T64> { using S = float;  using C = float;  using M = double; };
-
-template <typename T> __device__ __forceinline__ const Model<T>& pick(const Model<double>& d, const Model<float>& f);
-template <> __device__ __forceinline__ const Model<double>& pick<double>(const Model<double>& d, const Model<float>&) { return d; }
-template <> __device__ __forceinline__ const Model<float>& pick<float>(const Model<double>&, const Model<float>& f) { return f; }
-
-template <typename M>
-__device__ __forceinline__ uint32_t health_bits(const Macro<M>& q)
-{
-    uint32_t h = 0;
-    if (!(q.rho > M(0))) h |= H_RHO;
-    if (!(q.T > M(0))) h |= H_T;
-    if (!isfinite(q.rho) || !isfinite(q.T) || !isfinite(q.ux) || !isfinite(q.uy) || !isfinite(q.uz))
-        h |= H_NONFINITE;
-    return h;
-}
-
-// ---------------------------------------------------- NND flux, one axis --
-// Face values of the NND reconstruction along one axis for a velocity
-// component of sign SG (Sec. 3, Eq. (nnd)): with h = v g,
-//   v > 0:  g_{I+1/2} = f_I + mm(f_{I+1}-f_I, f_I-f_{I-1}) / 2
-//   v < 0:  g_{I+1/2} = f_{I+1} - mm(f_{I+1}-f_I, f_{I+2}-f_{I+1}) / 2
-// (the f^+ / f^- split with minmod odd and positively homogeneous).
-// Returns g_{I+1/2} - g_{I-1/2}; fm2..fp2 are f at I-2..I+2 (the two values
-// on the downwind far side are not used).
-template <int SG, typename C>
-__device__ __forceinline__ C nnd_diff(C fm2, C fm1, C f0, C fp1, C fp2)
-{
-    const C h = C(0.5);
-    if constexpr (SG > 0) {
-        const C dm = f0 - fm1, dp = fp1 - f0, dmm = fm1 - fm2;
-        const C gp = f0 + h * minmod(dp, dm);
-        const C gm = fm1 + h * minmod(dm, dmm);
-        return gp - gm;
-    } else {
-        const C dm = f0 - fm1, dp = fp1 - f0, dpp = fp2 - fp1;
-        const C gp = fp1 - h * minmod(dp, dpp);
-        const C gm = f0 - h * minmod(dm, dp);
-        return gp - gm;
-    }
-}
 
 // --------------------------------------------------------- the fused step --
 // One explicit step of Eq. (lp) with NND convection at every interior node:
@@ -136,6 +87,33 @@ k_step(Grid g, Model<double> md, Model<float> mf, const typename Types<MODE>::S*
     update_all<S, C>(f, fn, site, g.sv, g.sy, g.sz, fc, feq, mc);
 }
 
+// Tiled fused step: one workgroup per 64 x BY x TZ tile (see lbm3d_tile.h).
+// LBM3D_WAVES_PER_EU (build-time tuning knob): register budget of the tiled
+// kernel as wavefronts per SIMD (0 = compiler's choice).
+#ifndef LBM3D_WAVES_PER_EU
+#define LBM3D_WAVES_PER_EU 0
+#endif
+#if LBM3D_WAVES_PER_EU > 0
+#define LBM3D_TILED_ATTR __attribute__((amdgpu_waves_per_eu(LBM3D_WAVES_PER_EU)))
+#else
+#define LBM3D_TILED_ATTR
+#endif
+
+template <int MODE, int BY>
+__global__ void __launch_bounds__(TILE_X * BY) LBM3D_TILED_ATTR
+k_step_tiled(StepArgs<MODE> A, Model<double> md, Model<float> mf, int ntx, int nty, int tz)
+{
+    __shared__ TilePlane<BY, typename Types<MODE>::S> P;
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tyi = t % nty;
+    const int r = t / nty;
+    const int txi = r % ntx;
+    const int tzi = r / ntx;
+    const int z0 = tzi * tz;
+    const int z1 = min(z0 + tz, A.g.nz);
+    step_tile<MODE, BY>(A, md, mf, txi * TILE_X, tyi * BY, z0, z1, P);
+}
+
 // ------------------------------------------------------- initial state ----
 template <int MODE>
 __global__ void k_init(Grid g, Model<double> md, Model<float> mf, const double* __restrict__ q5,
@@ -181,7 +159,9 @@ __global__ void k_ghosts(Grid g, FaceBC bc, Model<double> md, Model<float> mf, d
     if (!((face_mask >> face) & 1)) return;
     const int axis = face >> 1, side = face & 1;
     const int n[3] = {g.nx, g.ny, g.nz};
-    const int t1 = (axis + 1) % 3, t2 = (axis + 2) % 3;
+    // tangential axes, x first where possible so that a wavefront writes
+    // consecutive addresses
+    const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
     const int64_t cnt = (int64_t)n[t1] * n[t2];
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= cnt) return;
@@ -395,26 +375,104 @@ hipError_t launch_init(int mode, const Grid& g, const Model<double>& md, const d
     return hipGetLastError();
 }
 
-hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const Model<double>& md,
+TileCfg default_tile(int mode, const Grid& g)
+{
+    TileCfg t;
+    t.by = mode == MODE_FP64 ? 4 : 8;
+    t.tz = mode == MODE_FP64 ? 32 : 16;
+    if (g.nz < 2 * t.tz) t.tz = std::max(1, g.nz / 4);
+    return t;
+}
+
+bool tile_supported(int mode, const TileCfg& t)
+{
+    if (t.tz < 1) return false;
+    if (t.by == 0) return true;
+    if (t.by == 2 || t.by == 4) return true;
+    return t.by == 8 && mode != MODE_FP64;
+}
+
+// LBM3D_FUSE_LAYERS (build-time tuning knob): 1 = the tiled step writes the
+// boundary layers it can, 0 = all layers are left to k_ghosts.
+#ifndef LBM3D_FUSE_LAYERS
+#define LBM3D_FUSE_LAYERS 1
+#endif
+
+uint32_t fused_faces(const Grid& g, const FaceBC& bc, const TileCfg& tc)
+{
+    if (tc.by == 0 || !LBM3D_FUSE_LAYERS) return 0u;  // the untiled kernel leaves all layers to k_ghosts
+    uint32_t m = 0;
+    for (int face = 0; face < 6; face++) {
+        const int k = bc.kind[face];
+        if (k == BC_PERIODIC || k == BC_REFLECT) m |= 1u << face;
+        // outflow along x pairs lanes of one wavefront: node n-1 and n-2 must
+        // share a 64-wide tile row
+        if (k == BC_OUTFLOW && face == 0) m |= 1u;
+        if (k == BC_OUTFLOW && face == 1 && (g.nx % TILE_X) != 1) m |= 2u;
+    }
+    return m;
+}
+
+uint32_t ghost_faces(const FaceBC& bc, uint32_t fused)
+{
+    uint32_t m = 0;
+    for (int face = 0; face < 6; face++)
+        if (bc.kind[face] != BC_INFLOW && !((fused >> face) & 1)) m |= 1u << face;
+    return m;
+}
+
+template <int MODE, int BY>
+static void launch_tiled(const Grid& g, const FaceBC& bc, uint32_t fused, int tz, const Model<double>& md,
+                         const Model<float>& mf, const void* f, void* fn, uint32_t* health, hipStream_t s)
+{
+    using S = typename Types<MODE>::S;
+    const int ntx = (g.nx + TILE_X - 1) / TILE_X;
+    const int nty = (g.ny + BY - 1) / BY;
+    const int ntz = (g.nz + tz - 1) / tz;
+    const int nb = ntx * nty * ntz;
+    StepArgs<MODE> A;
+    A.g = g;
+    A.bc = bc;
+    A.fused = fused;
+    A.f = (const S*)f;
+    A.fn = (S*)fn;
+    A.health = health;
+    k_step_tiled<MODE, BY><<<dim3(nb), dim3(TILE_X * BY), 0, s>>>(A, md, mf, ntx, nty, tz);
+}
+
+hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg& tc, const Model<double>& md,
                        const Model<float>& mf, const void* f, void* fn, uint32_t* health,
                        hipStream_t s)
 {
-    (void)bc;
+    if (tc.by != 0) {
+        const uint32_t fu = fused_faces(g, bc, tc);
+        switch (tc.by) {
+        case 2: LBM3D_DISPATCH(mode, launch_tiled<MD, 2>(g, bc, fu, tc.tz, md, mf, f, fn, health, s)); break;
+        case 8:
+            if (mode == MODE_FP64) return hipErrorInvalidValue;
+            if (mode == MODE_FP32) launch_tiled<MODE_FP32, 8>(g, bc, fu, tc.tz, md, mf, f, fn, health, s);
+            else launch_tiled<MODE_FP32_T64, 8>(g, bc, fu, tc.tz, md, mf, f, fn, health, s);
+            break;
+        default: LBM3D_DISPATCH(mode, launch_tiled<MD, 4>(g, bc, fu, tc.tz, md, mf, f, fn, health, s)); break;
+        }
+        return hipGetLastError();
+    }
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, g.nz);
     LBM3D_DISPATCH(mode, k_step<MD><<<grid, dim3(TX, TY), 0, s>>>(g, md, mf, (const typename Types<MD>::S*)f, (typename Types<MD>::S*)fn, health));
     return hipGetLastError();
 }
 
 hipError_t launch_ghosts(int mode, const Grid& g, const FaceBC& bc, const Model<double>& md,
-                         const double (*inflow)[5], bool include_fixed, void* f, hipStream_t s)
+                         const double (*inflow)[5], bool include_fixed, void* f, hipStream_t s,
+                         uint32_t face_mask)
 {
     const Model<float> mf = to_float(md);
     const int n[3] = {g.nx, g.ny, g.nz};
-    // faces are filled one launch per distinct inflow state (fixed faces
-    // carry their state as kernel arguments); everything else in one launch
+    // fixed-state faces are filled one launch each (their state travels as
+    // kernel arguments); the faces in face_mask in one launch
     int mask = 0;
     for (int face = 0; face < 6; face++)
-        if (bc.kind[face] != BC_INFLOW) mask |= 1 << face;
+        if (bc.kind[face] != BC_INFLOW && ((face_mask >> face) & 1)) mask |= 1 << face;
     int64_t maxcnt = 1;
     for (int a = 0; a < 3; a++) maxcnt = std::max<int64_t>(maxcnt, (int64_t)n[(a + 1) % 3] * n[(a + 2) % 3]);
     const unsigned nb = blocks_for(maxcnt, 256);

@@ -35,6 +35,7 @@ struct Grid {
     int32_t nx, ny, nz;
     int64_t sy, sz, sv;  // strides of y, z and velocity (elements)
     int64_t org;         // offset of interior node (0,0,0)
+    int64_t sink;        // offset (within a velocity plane) of an element that is never read
 };
 
 struct FaceBC {
@@ -67,11 +68,24 @@ struct SolveDesc {
 // ---- launches (lbm3d_device.hip) ----
 hipError_t launch_init(int mode, const Grid& g, const Model<double>& md, const double* q5,
                        void* f, hipStream_t s);
-hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const Model<double>& md,
+// Launch shape of the fused step: tile height BY (rows of 64 nodes; 0 selects
+// the untiled one-node-per-thread kernel) and the z extent TZ of a tile.
+struct TileCfg {
+    int by = 4;
+    int tz = 16;
+};
+TileCfg default_tile(int mode, const Grid& g);
+bool tile_supported(int mode, const TileCfg& t);
+// faces whose boundary layers the step kernel writes itself, and the
+// non-fixed faces left to the boundary-layer kernel
+uint32_t fused_faces(const Grid& g, const FaceBC& bc, const TileCfg& tc);
+uint32_t ghost_faces(const FaceBC& bc, uint32_t fused);
+hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg& tc, const Model<double>& md,
                        const Model<float>& mf, const void* f, void* fn, uint32_t* health,
                        hipStream_t s);
 hipError_t launch_ghosts(int mode, const Grid& g, const FaceBC& bc, const Model<double>& md,
-                         const double (*inflow)[5], bool include_fixed, void* f, hipStream_t s);
+                         const double (*inflow)[5], bool include_fixed, void* f, hipStream_t s,
+                         uint32_t face_mask = 0x3fu);
 hipError_t launch_moments(int mode, const Grid& g, const Model<double>& md, const void* f,
                           double* q5, hipStream_t s);
 hipError_t launch_conserved(int mode, const Grid& g, const Model<double>& md, const void* f,
@@ -84,7 +98,7 @@ hipError_t launch_batch_step(int mode, const SolveDesc* solves, const Tile* tile
 hipError_t launch_batch_ghosts(int mode, const SolveDesc* solves, int nsolves, int max_face,
                                hipStream_t s);
 
-// tile edge lengths of the step kernel (also the batched tiles)
-constexpr int TX = 64, TY = 4, TZ = 1;
+// block shape of the untiled step kernel
+constexpr int TX = 64, TY = 4;
 
 }  // namespace lbm3d

@@ -105,4 +105,57 @@ __device__ __forceinline__ void equilibrium(const Macro<M>& q, const Model<M>& m
     }
 }
 
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_INFLOW = 2, BC_REFLECT = 3 };
+enum { H_NONFINITE = 1u, H_RHO = 2u, H_T = 4u };
+
+// ----------------------------------------------------------------- types --
+template <int MODE> struct Types;
+template <> struct Types<MODE_FP64>     { using S = double; using C = double; using M = double; };
+template <> struct Types<MODE_FP32>     { using S = float;  using C = float;  using M = float;  };
+template <> struct Types<MODE_FP32_T64> { using S = float;  using C = float;  using M = double; };
+
+template <typename T> __device__ __forceinline__ const Model<T>& pick(const Model<double>& d, const Model<float>& f);
+template <> __device__ __forceinline__ const Model<double>& pick<double>(const Model<double>& d, const Model<float>&) { return d; }
+template <> __device__ __forceinline__ const Model<float>& pick<float>(const Model<double>&, const Model<float>& f) { return f; }
+
+template <typename M>
+__device__ __forceinline__ uint32_t health_bits(const Macro<M>& q)
+{
+    uint32_t h = 0;
+    if (!(q.rho > M(0))) h |= H_RHO;
+    if (!(q.T > M(0))) h |= H_T;
+    if (!isfinite(q.rho) || !isfinite(q.T) || !isfinite(q.ux) || !isfinite(q.uy) || !isfinite(q.uz))
+        h |= H_NONFINITE;
+    return h;
+}
+
+// ---------------------------------------------------- NND flux, one axis --
+// Face values of the NND reconstruction along one axis for a velocity
+// component of sign SG (Sec. 3, Eq. (nnd)): with h = v g,
+//   v > 0:  g_{I+1/2} = f_I + mm(f_{I+1}-f_I, f_I-f_{I-1}) / 2
+//   v < 0:  g_{I+1/2} = f_{I+1} - mm(f_{I+1}-f_I, f_{I+2}-f_{I+1}) / 2
+// (the f^+ / f^- split with minmod odd and positively homogeneous).
+// Returns g_{I+1/2} - g_{I-1/2}; fm2..fp2 are f at I-2..I+2 (the two values
+// on the downwind far side are not used).
+// Face value g_{I+1/2} for v > 0 from f_{I-1}, f_I, f_{I+1}.
+template <typename C>
+__device__ __forceinline__ C face_pos(C fm1, C f0, C fp1)
+{
+    return f0 + C(0.5) * minmod(fp1 - f0, f0 - fm1);
+}
+// Face value g_{I+1/2} for v < 0 from f_I, f_{I+1}, f_{I+2}.
+template <typename C>
+__device__ __forceinline__ C face_neg(C f0, C fp1, C fp2)
+{
+    return fp1 - C(0.5) * minmod(fp1 - f0, fp2 - fp1);
+}
+template <int SG, typename C>
+__device__ __forceinline__ C nnd_diff(C fm2, C fm1, C f0, C fp1, C fp2)
+{
+    if constexpr (SG > 0)
+        return face_pos(fm1, f0, fp1) - face_pos(fm2, fm1, f0);
+    else
+        return face_neg(f0, fp1, fp2) - face_neg(fm1, f0, fp1);
+}
+
 }  // namespace lbm3d

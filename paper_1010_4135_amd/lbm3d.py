@@ -71,6 +71,8 @@ def _load():
         "lbm3d_step": (I32, [P, I64]),
         "lbm3d_step_timed": (I32, [P, I64, D]),
         "lbm3d_step_profiled": (I32, [P, I64, D, D]),
+        "lbm3d_set_tile": (I32, [P, I32, I32]),
+        "lbm3d_get_tile": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "lbm3d_sync": (I32, [P]),
         "lbm3d_moments": (I32, [P, D, D, D, D, D]),
         "lbm3d_conserved": (I32, [P, D]),
@@ -196,6 +198,17 @@ def lbm3d_step_profiled(h, nsteps: int):
     _check(_lib.lbm3d_step_profiled(h, int(nsteps), ctypes.byref(tot), ctypes.byref(ker)),
            "lbm3d_step_profiled")
     return tot.value, ker.value
+
+
+def lbm3d_set_tile(h, by: int, tz: int):
+    _check(_lib.lbm3d_set_tile(h, int(by), int(tz)), "lbm3d_set_tile")
+
+
+def lbm3d_get_tile(h):
+    by = ctypes.c_int32(0)
+    tz = ctypes.c_int32(0)
+    _check(_lib.lbm3d_get_tile(h, ctypes.byref(by), ctypes.byref(tz)), "lbm3d_get_tile")
+    return by.value, tz.value
 
 
 def lbm3d_sync(h):
@@ -324,6 +337,12 @@ class Solver:
 
     def sync(self):
         lbm3d_sync(self.h)
+
+    def set_tile(self, by: int, tz: int):
+        lbm3d_set_tile(self.h, by, tz)
+
+    def get_tile(self):
+        return lbm3d_get_tile(self.h)
 
     def moments(self, allow_nonfinite: bool = False):
         return lbm3d_moments(self.h, self.shape, allow_nonfinite)

@@ -215,3 +215,27 @@ def test_step_before_init_is_rejected():
     with pytest.raises(lbm3d.LbmError) as ei:
         s.init(*[np.zeros((8, 8, 8))] * 5)
     assert ei.value.code == lbm3d.E_INVAL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_t64"])
+def test_results_do_not_depend_on_tile_shape(precision):
+    """Every launch shape (untiled, and 64 x BY x TZ tiles with ragged edges
+    in x, y and z) gives bitwise the same distributions."""
+    lbm3d = _lib()
+    case = inputs.shock_bubble(11, grid=(70, 19, 13), precision=precision, mach=3.0, ratio=0.4)
+    shapes = [(0, 1), (2, 1), (2, 5), (4, 3), (4, 16)]
+    if precision != "fp64":
+        shapes += [(8, 2), (8, 13)]
+    ref = None
+    for by, tz in shapes:
+        s = lbm3d.Solver(dict(case.params))
+        s.set_tile(by, tz)
+        assert s.get_tile() == (by, tz)
+        s.init(*case.fields)
+        s.step(21)
+        f = s.get_f()
+        s.close()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f, ref), (by, tz)
