@@ -1,17 +1,224 @@
-// Batched step over many solves (placeholder until the persistent kernel lands).
-#include "lbm3d_api_impl.h"
+// Batched stepping: many solves of uneven size advanced by one persistent
+// launch per step over a packed tile list, with step runs replayed from a
+// captured HIP graph.
+#include "lbm3d_batch.h"
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <set>
+
+namespace lbm3d {
+
+static int32_t herr(hipError_t e)
+{
+    return e == hipSuccess ? LBM3D_OK : (e == hipErrorOutOfMemory ? LBM3D_E_NOMEM : LBM3D_E_DEVICE);
+}
+
+// Steps per captured graph of the batched step (even: parities 0,1,...).
+constexpr int BATCH_GRAPH_STEPS = 16;
+
+BatchPlan::~BatchPlan()
+{
+    release_graph();
+    if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
+    if (dmem_) (void)hipFree(dmem_);
+}
+
+void BatchPlan::release_graph()
+{
+    if (graph_) (void)hipGraphExecDestroy(graph_);
+    graph_ = nullptr;
+}
+
+int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t s)
+{
+    release_graph();
+    members_ = members;
+    ntiles_ = 0;
+    parity_ = 0;
+    if (members.empty()) return LBM3D_OK;
+    mode_ = members[0]->mode;
+    by_ = mode_ == LBM3D_FP64 ? 4 : 8;
+    tz_ = 8;
+
+    // packed tile list: each solve's tiles in (z chunk, x, y) order, split
+    // into eight contiguous runs interleaved so that run c lands on XCD c
+    // (workgroup b runs tiles b, b + G, ... with G a multiple of 8)
+    std::vector<BatchTile> order;
+    std::vector<BatchSolve> table(members.size());
+    ghost_rest_.assign(members.size(), 0u);
+    cur0_.assign(members.size(), 0);
+    for (size_t k = 0; k < members.size(); k++) {
+        lbm3d_solver* h = members[k];
+        TileCfg tc;
+        tc.by = by_;
+        tc.tz = tz_;
+        BatchSolve& d = table[k];
+        std::memset(&d, 0, sizeof(d));
+        d.g = h->g;
+        d.bc = h->bc;
+        d.fused = fused_faces(h->g, h->bc, tc);
+        d.cur0 = h->cur;
+        d.f[0] = h->f[0];
+        d.f[1] = h->f[1];
+        d.health = h->health;
+        d.md = h->md;
+        d.mf = h->mf;
+        ghost_rest_[k] = ghost_faces(h->bc, d.fused);
+        cur0_[k] = h->cur;
+        const int ntx = (h->g.nx + TILE_X - 1) / TILE_X;
+        const int nty = (h->g.ny + by_ - 1) / by_;
+        for (int z0 = 0; z0 < h->g.nz; z0 += tz_)
+            for (int tx = 0; tx < ntx; tx++)
+                for (int ty = 0; ty < nty; ty++) {
+                    BatchTile t;
+                    t.solve = (int32_t)k;
+                    t.txi = (int16_t)tx;
+                    t.tyi = (int16_t)ty;
+                    t.z0 = (int16_t)z0;
+                    t.z1 = (int16_t)std::min(z0 + tz_, h->g.nz);
+                    order.push_back(t);
+                }
+    }
+    const int n = (int)order.size();
+    std::vector<BatchTile> tiles(n);
+    const int per = n / 8, rem = n % 8;
+    int pos = 0;
+    for (int c = 0; c < 8; c++) {
+        // slots c, c+8, c+16, ... (all < n) take run c of the natural order
+        const int cnt = per + (c < rem ? 1 : 0);
+        for (int j = 0; j < cnt; j++) tiles[8 * j + c] = order[pos + j];
+        pos += cnt;
+    }
+    ntiles_ = n;
+    // persistent grid: a multiple of 8 workgroups, about what the GPU holds
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    nblocks_ = std::min(n, cus * 3);
+    if (nblocks_ >= 8) nblocks_ -= nblocks_ % 8;
+
+    const size_t sb = table.size() * sizeof(BatchSolve);
+    const size_t need = sb + (size_t)n * sizeof(BatchTile) + 256;
+    if (need > dbytes_) {
+        if (dmem_) (void)hipFree(dmem_);
+        dmem_ = nullptr;
+        dbytes_ = 0;
+        hipError_t e = hipMalloc(&dmem_, need);
+        if (e != hipSuccess) return herr(e);
+        dbytes_ = need;
+    }
+    dsolves_ = (BatchSolve*)dmem_;
+    dtiles_ = (BatchTile*)((char*)dmem_ + ((sb + 255) / 256) * 256);
+    hipError_t e = hipMemcpyAsync(dsolves_, table.data(), sb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dtiles_, tiles.data(), (size_t)n * sizeof(BatchTile), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables die at return
+    return herr(e);
+}
+
+hipError_t BatchPlan::enqueue(int parity, hipStream_t s)
+{
+    hipError_t e = launch_batch_step(mode_, by_, dsolves_, dtiles_, ntiles_, nblocks_, parity, s);
+    if (e != hipSuccess) return e;
+    // faces whose layers the step cannot write (rare): the boundary kernel
+    for (size_t k = 0; k < members_.size(); k++) {
+        if (!ghost_rest_[k]) continue;
+        lbm3d_solver* h = members_[k];
+        const int cur = cur0_[k] ^ parity;
+        e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[cur ^ 1], s, ghost_rest_[k]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int32_t BatchPlan::run(int64_t k, hipStream_t s)
+{
+    if (members_.empty() || k <= 0) return LBM3D_OK;
+    int64_t left = k;
+    // align to an even parity so the captured graph (parities 0,1,...) applies
+    if (parity_ & 1) {
+        hipError_t e = enqueue(1, s);
+        if (e != hipSuccess) return herr(e);
+        parity_ ^= 1;
+        left--;
+    }
+    while (left >= BATCH_GRAPH_STEPS) {
+        if (!graph_) {
+            if (!capture_stream_) {
+                hipError_t e = hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking);
+                if (e != hipSuccess) return herr(e);
+            }
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return herr(e);
+            for (int j = 0; j < BATCH_GRAPH_STEPS && e == hipSuccess; j++) e = enqueue(j & 1, capture_stream_);
+            hipError_t e2 = hipStreamEndCapture(capture_stream_, &graph);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return herr(e != hipSuccess ? e : e2);
+            }
+            e = hipGraphInstantiate(&graph_, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return herr(e);
+        }
+        hipError_t e = hipGraphLaunch(graph_, s);
+        if (e != hipSuccess) return herr(e);
+        left -= BATCH_GRAPH_STEPS;
+    }
+    for (; left > 0; left--) {
+        hipError_t e = enqueue(parity_, s);
+        if (e != hipSuccess) return herr(e);
+        parity_ ^= 1;
+    }
+    // members advance by k steps; their current buffer flips with odd k (the
+    // device table keeps the build-time buffers and parity_ the offset)
+    for (lbm3d_solver* h : members_) {
+        h->steps += k;
+        if (k & 1) h->cur ^= 1;
+    }
+    return LBM3D_OK;
+}
+
+}  // namespace lbm3d
+
+// ------------------------------------------------------------------- C ABI --
+using namespace lbm3d;
 
 extern "C" int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* nsteps)
 {
     if (!hs || !nsteps || count < 1) return LBM3D_E_INVAL;
+    std::set<lbm3d_t> seen;
     for (int32_t k = 0; k < count; k++) {
-        if (!hs[k] || nsteps[k] < 0) return LBM3D_E_INVAL;
-        int32_t rc = lbm3d_step(hs[k], nsteps[k]);
-        if (rc) return rc;
+        if (!hs[k] || nsteps[k] < 0 || !seen.insert(hs[k]).second) return LBM3D_E_INVAL;
+        if (!hs[k]->initialised) return LBM3D_E_STATE;
+        if (hs[k]->mode != hs[0]->mode) return LBM3D_E_INVAL;
     }
-    for (int32_t k = 0; k < count; k++) {
-        int32_t rc = lbm3d_sync(hs[k]);
+    hipStream_t s = hs[0]->stream;
+    // work already queued on the other solves' streams precedes the batch
+    for (int32_t k = 1; k < count; k++)
+        if (hs[k]->stream != s && hipStreamSynchronize(hs[k]->stream) != hipSuccess) return LBM3D_E_DEVICE;
+    std::vector<int64_t> left(nsteps, nsteps + count);
+    BatchPlan plan;
+    for (;;) {
+        std::vector<lbm3d_solver*> active;
+        int64_t k = 0;
+        for (int32_t j = 0; j < count; j++)
+            if (left[j] > 0) {
+                active.push_back(hs[j]);
+                k = (k == 0) ? left[j] : std::min(k, left[j]);
+            }
+        if (active.empty()) break;
+        int32_t rc = plan.build(active, s);
         if (rc) return rc;
+        rc = plan.run(k, s);
+        if (rc) return rc;
+        for (int32_t j = 0; j < count; j++)
+            if (left[j] > 0) left[j] -= k;
     }
-    return LBM3D_OK;
+    return hipStreamSynchronize(s) == hipSuccess ? LBM3D_OK : LBM3D_E_DEVICE;
 }

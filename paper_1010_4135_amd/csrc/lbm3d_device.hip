@@ -114,6 +114,32 @@ k_step_tiled(StepArgs<MODE> A, Model<double> md, Model<float> mf, int ntx, int n
     step_tile<MODE, BY>(A, md, mf, txi * TILE_X, tyi * BY, z0, z1, P);
 }
 
+// Batched fused step: persistent workgroups walk a packed list of tiles from
+// many solves (any sizes, one precision), each tile advanced by the same
+// step_tile body as a single solve, so every solve's result is bitwise the
+// same alone or in any batch.
+template <int MODE, int BY>
+__global__ void __launch_bounds__(TILE_X * BY) LBM3D_TILED_ATTR
+k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict__ tiles, int ntiles, int parity)
+{
+    using S = typename Types<MODE>::S;
+    __shared__ TilePlane<BY, S> P;
+    for (int t = (int)blockIdx.x; t < ntiles; t += (int)gridDim.x) {
+        const BatchTile tile = tiles[t];
+        const BatchSolve& d = solves[tile.solve];
+        StepArgs<MODE> A;
+        A.g = d.g;
+        A.bc = d.bc;
+        A.fused = d.fused;
+        const int cur = d.cur0 ^ parity;
+        A.f = (const S*)d.f[cur];
+        A.fn = (S*)d.f[cur ^ 1];
+        A.health = d.health;
+        step_tile<MODE, BY>(A, d.md, d.mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
+        lds_barrier();  // the plane buffer is reused by the next tile
+    }
+}
+
 // ------------------------------------------------------- initial state ----
 template <int MODE>
 __global__ void k_init(Grid g, Model<double> md, Model<float> mf, const double* __restrict__ q5,
@@ -146,92 +172,56 @@ __global__ void k_init(Grid g, Model<double> md, Model<float> mf, const double* 
 // fixed state; linear extrapolation of (rho, u, T) from the two nodes next
 // to the face; reflection (wall layer: the node next to the face with zero
 // normal velocity; mirror layer: its normal velocity negated); distributions
-// are f^eq of those values.  Periodic faces copy f from the other side.
-// Only face layers are written: the stencils never read edges or corners.
+// are f^eq of those values.  Periodic faces copy f from the other side.  One
+// thread per line of nodes perpendicular to a face (x fastest on the y and z
+// faces), all requested faces in one launch; the per-line work is the same
+// layer_line routine the tiled step uses for the layers it writes itself,
+// so both paths produce identical layers.  Only face layers are written:
+// the stencils never read edges or corners.
+struct FixedStates {
+    double q[6][5];  // (rho, ux, uy, uz, T) per fixed-state face
+};
+
 template <int MODE>
-__global__ void k_ghosts(Grid g, FaceBC bc, Model<double> md, Model<float> mf, double4 fixed_q,
-                         double fixed_T, int face_mask, typename Types<MODE>::S* __restrict__ f)
+__global__ void __launch_bounds__(64)
+k_layers(StepArgs<MODE> A, Model<double> md, Model<float> mf, FixedStates fx, uint32_t faces)
 {
-    using S = typename Types<MODE>::S;
     using C = typename Types<MODE>::C;
     using M = typename Types<MODE>::M;
-    const int face = blockIdx.z;
-    if (!((face_mask >> face) & 1)) return;
-    const int axis = face >> 1, side = face & 1;
-    const int n[3] = {g.nx, g.ny, g.nz};
-    // tangential axes, x first where possible so that a wavefront writes
-    // consecutive addresses
-    const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
-    const int64_t cnt = (int64_t)n[t1] * n[t2];
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= cnt) return;
-    const int64_t st[3] = {1, g.sy, g.sz};
-    const int b1 = (int)(k % n[t1]), b2 = (int)(k / n[t1]);
-    const int64_t base = g.org + b1 * st[t1] + (int64_t)b2 * st[t2];
-    const int64_t sa = st[axis];
-    const int na = n[axis];
-    // ghost coordinates along the axis and the interior nodes next to the face
-    const int g1 = side ? na : -1, g2 = side ? na + 1 : -2;
-    const int i0 = side ? na - 1 : 0, i1 = side ? na - 2 : 1;
-    const int kind = bc.kind[face];
-    if (kind == BC_PERIODIC) {
-        const int w1 = ((g1 % na) + na) % na, w2 = ((g2 % na) + na) % na;
+    const Grid& g = A.g;
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 #pragma unroll
-        for (int i = 0; i < NV; i++) {
-            S* fi = f + i * g.sv + base;
-            fi[g1 * sa] = fi[w1 * sa];
-            fi[g2 * sa] = fi[w2 * sa];
+    for (int face = 0; face < 6; face++) {
+        if (!((faces >> face) & 1)) continue;
+        const int axis = face >> 1;
+        const int64_t cnt = axis == 0 ? (int64_t)g.ny * g.nz : axis == 1 ? (int64_t)g.nx * g.nz : (int64_t)g.nx * g.ny;
+        if (j >= cnt) {
+            j -= cnt;
+            continue;
+        }
+        int cx = 0, cy = 0, cz = 0;
+        if (axis == 0) { cy = (int)(j % g.ny); cz = (int)(j / g.ny); }
+        else if (axis == 1) { cx = (int)(j % g.nx); cz = (int)(j / g.nx); }
+        else { cx = (int)(j % g.nx); cy = (int)(j / g.nx); }
+        const uint32_t line = (uint32_t)(g.org + (int64_t)cz * g.sz + (int64_t)cy * g.sy + cx);
+        const uint32_t st = axis == 0 ? 1u : axis == 1 ? (uint32_t)g.sy : (uint32_t)g.sz;
+        const int n = axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz;
+        if (A.bc.kind[face] == BC_INFLOW) {
+            Macro<M> q;
+            q.rho = static_cast<M>(fx.q[face][0]);
+            q.ux = static_cast<M>(fx.q[face][1]);
+            q.uy = static_cast<M>(fx.q[face][2]);
+            q.uz = static_cast<M>(fx.q[face][3]);
+            q.T = static_cast<M>(fx.q[face][4]);
+            C e[NV];
+            equilibrium<C, M>(q, pick<M>(md, mf), pick<C>(md, mf), e);
+            const int side = face & 1;
+            store_node(A.fn, g.sv, line + (uint32_t)(side ? n : -1) * st, e);
+            store_node(A.fn, g.sv, line + (uint32_t)(side ? n + 1 : -2) * st, e);
+        } else {
+            layer_line<MODE>(A, pick<M>(md, mf), pick<C>(md, mf), face, line, st, n, 0, n);
         }
         return;
-    }
-    const Model<C>& mc = pick<C>(md, mf);
-    const Model<M>& mm = pick<M>(md, mf);
-    Macro<M> q1, q2;
-    if (kind == BC_INFLOW) {
-        // fixed state of the face being filled: (rho, ux, uy, uz) and T
-        q1.rho = static_cast<M>(fixed_q.x);
-        q1.ux = static_cast<M>(fixed_q.y);
-        q1.uy = static_cast<M>(fixed_q.z);
-        q1.uz = static_cast<M>(fixed_q.w);
-        q1.T = static_cast<M>(fixed_T);
-        q2 = q1;
-    } else {
-        C fa[NV];
-#pragma unroll
-        for (int i = 0; i < NV; i++) fa[i] = static_cast<C>(f[i * g.sv + base + i0 * sa]);
-        const Macro<M> qa = moments<M, C>(fa, mm);
-        if (kind == BC_OUTFLOW) {
-            C fb[NV];
-#pragma unroll
-            for (int i = 0; i < NV; i++) fb[i] = static_cast<C>(f[i * g.sv + base + i1 * sa]);
-            const Macro<M> qb = moments<M, C>(fb, mm);
-            q1.rho = M(2) * qa.rho - qb.rho;
-            q1.ux = M(2) * qa.ux - qb.ux;
-            q1.uy = M(2) * qa.uy - qb.uy;
-            q1.uz = M(2) * qa.uz - qb.uz;
-            q1.T = M(2) * qa.T - qb.T;
-            q2.rho = M(2) * q1.rho - qa.rho;
-            q2.ux = M(2) * q1.ux - qa.ux;
-            q2.uy = M(2) * q1.uy - qa.uy;
-            q2.uz = M(2) * q1.uz - qa.uz;
-            q2.T = M(2) * q1.T - qa.T;
-        } else {  // BC_REFLECT
-            q1 = qa;
-            q2 = qa;
-            M* n1 = axis == 0 ? &q1.ux : (axis == 1 ? &q1.uy : &q1.uz);
-            M* n2 = axis == 0 ? &q2.ux : (axis == 1 ? &q2.uy : &q2.uz);
-            *n1 = M(0);
-            *n2 = -*n2;
-        }
-    }
-    C e1[NV], e2[NV];
-    equilibrium<C, M>(q1, mm, mc, e1);
-    equilibrium<C, M>(q2, mm, mc, e2);
-#pragma unroll
-    for (int i = 0; i < NV; i++) {
-        S* fi = f + i * g.sv + base;
-        fi[g1 * sa] = static_cast<S>(e1[i]);
-        fi[g2 * sa] = static_cast<S>(e2[i]);
     }
 }
 
@@ -377,10 +367,12 @@ hipError_t launch_init(int mode, const Grid& g, const Model<double>& md, const d
 
 TileCfg default_tile(int mode, const Grid& g)
 {
+    // measured on MI355X at 256x128x128: 64x8x32 tiles (FP32 modes) and
+    // 64x4x64 (FP64); a short z extent leaves too few workgroups on small grids
     TileCfg t;
     t.by = mode == MODE_FP64 ? 4 : 8;
-    t.tz = mode == MODE_FP64 ? 32 : 16;
-    if (g.nz < 2 * t.tz) t.tz = std::max(1, g.nz / 4);
+    t.tz = mode == MODE_FP64 ? 64 : 32;
+    if (g.nz < 2 * t.tz) t.tz = std::max(2, g.nz / 4);
     return t;
 }
 
@@ -392,23 +384,21 @@ bool tile_supported(int mode, const TileCfg& t)
     return t.by == 8 && mode != MODE_FP64;
 }
 
-// LBM3D_FUSE_LAYERS (build-time tuning knob): 1 = the tiled step writes the
-// boundary layers it can, 0 = all layers are left to k_ghosts.
-#ifndef LBM3D_FUSE_LAYERS
-#define LBM3D_FUSE_LAYERS 1
-#endif
-
 uint32_t fused_faces(const Grid& g, const FaceBC& bc, const TileCfg& tc)
 {
-    if (tc.by == 0 || !LBM3D_FUSE_LAYERS) return 0u;  // the untiled kernel leaves all layers to k_ghosts
+    if (tc.by == 0 || !LBM3D_FUSE_LAYERS) return 0u;  // layers left to the boundary-layer kernel
     uint32_t m = 0;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int ext[3] = {TILE_X, tc.by, tc.tz};  // tile extent per axis
     for (int face = 0; face < 6; face++) {
-        const int k = bc.kind[face];
+        const int k = bc.kind[face], a = face >> 1;
         if (k == BC_PERIODIC || k == BC_REFLECT) m |= 1u << face;
-        // outflow along x pairs lanes of one wavefront: node n-1 and n-2 must
-        // share a 64-wide tile row
-        if (k == BC_OUTFLOW && face == 0) m |= 1u;
-        if (k == BC_OUTFLOW && face == 1 && (g.nx % TILE_X) != 1) m |= 2u;
+        // extrapolation reads the two nodes next to the face: both must lie
+        // in one tile (tiles start at multiples of the extent from 0)
+        if (k == BC_OUTFLOW && ext[a] >= 2) {
+            const bool ok = (face & 1) ? ((n[a] - 1) % ext[a]) != 0 : true;
+            if (ok) m |= 1u << face;
+        }
     }
     return m;
 }
@@ -467,32 +457,39 @@ hipError_t launch_ghosts(int mode, const Grid& g, const FaceBC& bc, const Model<
                          uint32_t face_mask)
 {
     const Model<float> mf = to_float(md);
-    const int n[3] = {g.nx, g.ny, g.nz};
-    // fixed-state faces are filled one launch each (their state travels as
-    // kernel arguments); the faces in face_mask in one launch
-    int mask = 0;
-    for (int face = 0; face < 6; face++)
-        if (bc.kind[face] != BC_INFLOW && ((face_mask >> face) & 1)) mask |= 1 << face;
-    int64_t maxcnt = 1;
-    for (int a = 0; a < 3; a++) maxcnt = std::max<int64_t>(maxcnt, (int64_t)n[(a + 1) % 3] * n[(a + 2) % 3]);
-    const unsigned nb = blocks_for(maxcnt, 256);
-    if (mask) {
-        LBM3D_DISPATCH(mode, k_ghosts<MD><<<dim3(nb, 1, 6), dim3(256), 0, s>>>(g, bc, md, mf, double4{0, 0, 0, 0}, 0.0, mask, (typename Types<MD>::S*)f));
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (include_fixed) {
-        for (int face = 0; face < 6; face++) {
-            if (bc.kind[face] != BC_INFLOW) continue;
+    uint32_t faces = 0;
+    int64_t lines = 0;
+    FixedStates fx{};
+    for (int face = 0; face < 6; face++) {
+        const bool fixed = bc.kind[face] == BC_INFLOW;
+        if (fixed ? !include_fixed : !((face_mask >> face) & 1)) continue;
+        faces |= 1u << face;
+        const int axis = face >> 1;
+        lines += axis == 0 ? (int64_t)g.ny * g.nz : axis == 1 ? (int64_t)g.nx * g.nz : (int64_t)g.nx * g.ny;
+        if (fixed) {
             const double* st = inflow[face];
-            const double4 q{st[0], st[1], st[2], st[3]};
-            const double T = st[4] / st[0];
-            LBM3D_DISPATCH(mode, k_ghosts<MD><<<dim3(nb, 1, 6), dim3(256), 0, s>>>(g, bc, md, mf, q, T, 1 << face, (typename Types<MD>::S*)f));
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
+            fx.q[face][0] = st[0];
+            fx.q[face][1] = st[1];
+            fx.q[face][2] = st[2];
+            fx.q[face][3] = st[3];
+            fx.q[face][4] = st[4] / st[0];  // T = p / rho
         }
     }
-    return hipSuccess;
+    if (!faces) return hipSuccess;
+    // one wavefront per block: the x-face lines (scattered rows) then spread
+    // over every CU instead of crowding the first few
+    const unsigned nb = blocks_for(lines, 64);
+    LBM3D_DISPATCH(mode, {
+        StepArgs<MD> A{};
+        A.g = g;
+        A.bc = bc;
+        A.fused = 0;
+        A.f = nullptr;
+        A.fn = (typename Types<MD>::S*)f;
+        A.health = nullptr;
+        k_layers<MD><<<dim3(nb), dim3(64), 0, s>>>(A, md, mf, fx, faces);
+    });
+    return hipGetLastError();
 }
 
 hipError_t launch_moments(int mode, const Grid& g, const Model<double>& md, const void* f, double* q5,
@@ -532,14 +529,22 @@ hipError_t launch_pack(int mode, const Grid& g, const void* f, void* dense, bool
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step(int, const SolveDesc*, const Tile*, int, int, hipStream_t)
+hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles, int ntiles,
+                             int nblocks, int parity, hipStream_t s)
 {
-    return hipErrorNotSupported;
-}
-
-hipError_t launch_batch_ghosts(int, const SolveDesc*, int, int, hipStream_t)
-{
-    return hipErrorNotSupported;
+    if (ntiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)std::max(1, std::min(nblocks, ntiles)));
+    switch (by) {
+    case 2: LBM3D_DISPATCH(mode, k_batch_step<MD, 2><<<grid, dim3(TILE_X * 2), 0, s>>>(solves, tiles, ntiles, parity)); break;
+    case 8:
+        if (mode == MODE_FP64) return hipErrorInvalidValue;
+        if (mode == MODE_FP32) k_batch_step<MODE_FP32, 8><<<grid, dim3(TILE_X * 8), 0, s>>>(solves, tiles, ntiles, parity);
+        else k_batch_step<MODE_FP32_T64, 8><<<grid, dim3(TILE_X * 8), 0, s>>>(solves, tiles, ntiles, parity);
+        break;
+    case 4: LBM3D_DISPATCH(mode, k_batch_step<MD, 4><<<grid, dim3(TILE_X * 4), 0, s>>>(solves, tiles, ntiles, parity)); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace lbm3d

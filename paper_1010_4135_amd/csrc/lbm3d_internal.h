@@ -47,20 +47,21 @@ struct Device;  // per-solve device pointers, defined in lbm3d_api.cpp
 // Precision modes (same values as the ABI enum).
 enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_FP32_T64 = 2 };
 
-// One tile of the batched step: a box of interior nodes of one solve.
-struct Tile {
+// One tile of the batched step: a 64 x BY x (z1 - z0) box of one solve.
+struct BatchTile {
     int32_t solve;        // index into the solve table
-    int32_t x0, y0, z0;   // first interior node
+    int16_t txi, tyi;     // tile column (x0 = 64 txi, y0 = BY tyi)
+    int16_t z0, z1;       // z range
 };
 
-// Per-solve entry of the batched step.
-struct SolveDesc {
-    const void* f;        // current distributions (storage type)
-    void* fn;             // next distributions
-    uint32_t* health;
+// Per-solve entry of the batched step (device memory, read uniformly).
+struct BatchSolve {
     Grid g;
     FaceBC bc;
-    int32_t pad;
+    uint32_t fused;       // faces whose boundary layers the step writes itself
+    int32_t cur0;         // buffer holding the current level at batch step 0
+    void* f[2];           // the two distribution buffers
+    uint32_t* health;
     Model<double> md;
     Model<float> mf;
 };
@@ -93,12 +94,13 @@ hipError_t launch_conserved(int mode, const Grid& g, const Model<double>& md, co
 int conserved_blocks(const Grid& g);
 hipError_t launch_pack(int mode, const Grid& g, const void* f, void* dense, bool to_dense,
                        hipStream_t s);
-hipError_t launch_batch_step(int mode, const SolveDesc* solves, const Tile* tiles, int ntiles,
-                             int nblocks, hipStream_t s);
-hipError_t launch_batch_ghosts(int mode, const SolveDesc* solves, int nsolves, int max_face,
-                               hipStream_t s);
+// One step of every solve in `solves` (device table) over the packed tile
+// list (device); `parity` selects f[cur0 ^ parity] as the current level.
+hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles, int ntiles,
+                             int nblocks, int parity, hipStream_t s);
 
-// block shape of the untiled step kernel
+// block shape of the untiled step kernel; x extent of a tile of the tiled one
 constexpr int TX = 64, TY = 4;
+constexpr int TILE_X = 64;
 
 }  // namespace lbm3d

@@ -18,8 +18,8 @@
 //   - moments, equilibrium, NND convection in x, y, z, dissipation and the
 //     BGK forward-Euler update are evaluated in registers and each new f is
 //     written once;
-//   - nodes next to a periodic or reflecting face (and to an x outflow face)
-//     also write the boundary layers of the new level, so no second kernel
+//   - tiles next to a periodic, reflecting or extrapolating face then write
+//     the boundary layers of the new level themselves, so no second kernel
 //     is needed for them.
 // Per node, the arithmetic is the same sequence of operations as a direct
 // evaluation of the stencil, so results do not depend on the tile shape.
@@ -29,13 +29,17 @@
 
 namespace lbm3d {
 
-constexpr int TILE_X = 64;
-
 // Build-time tuning knobs of the sweep (defaults are the tuned choice):
 // LBM3D_HALO_PREFETCH loads the next plane's halo during the current
 // plane's compute (1) or right before staging it (0).
 #ifndef LBM3D_HALO_PREFETCH
 #define LBM3D_HALO_PREFETCH 1
+#endif
+// LBM3D_FUSE_LAYERS: 1 = the tiled step writes the boundary layers whose
+// source nodes a tile owns (after its sweep); 0 = a separate launch of the
+// boundary-layer kernel writes all of them.
+#ifndef LBM3D_FUSE_LAYERS
+#define LBM3D_FUSE_LAYERS 0
 #endif
 
 // Workgroup barrier that orders LDS accesses only: global loads in flight
@@ -144,30 +148,69 @@ __device__ __forceinline__ void store_node(S* __restrict__ fn, int64_t sv, uint3
     for (int i = 0; i < NV; i++) (fn + i * sv)[off] = static_cast<S>(v[i]);
 }
 
-template <typename M>
-__device__ __forceinline__ Macro<M> shfl_macro(const Macro<M>& q, int src_lane)
+// Does a tile owning nodes [lo, hi) along an axis of n nodes write layer
+// nodes of this face?  Periodic: a layer node copies node (slot mod n), and
+// the owner of that node writes it.  Reflecting / extrapolating: the owner
+// of the node next to the face (the host fuses an extrapolating face only if
+// the second node in lies in the same tile).
+__device__ __forceinline__ bool layer_owner(int kind, int side, int n, int lo, int hi)
 {
-    Macro<M> r;
-    r.rho = __shfl(q.rho, src_lane);
-    r.ux = __shfl(q.ux, src_lane);
-    r.uy = __shfl(q.uy, src_lane);
-    r.uz = __shfl(q.uz, src_lane);
-    r.T = __shfl(q.T, src_lane);
-    return r;
+    if (kind == BC_INFLOW) return false;
+    if (kind == BC_PERIODIC) {
+        const int s1 = side ? (n % n) : (((-1 % n) + n) % n);
+        const int s2 = side ? ((n + 1) % n) : (((-2 % n) + n) % n);
+        return (s1 >= lo && s1 < hi) || (s2 >= lo && s2 < hi);
+    }
+    const int i0 = side ? n - 1 : 0;
+    return i0 >= lo && i0 < hi;
 }
 
-// Periodic copies: bit k set if boundary-layer slot k (-2, -1, n, n+1) of an
-// axis of n nodes is a copy of node c.
-__device__ __forceinline__ int wrap_mask(int c, int n)
+// Layer nodes of one face on the line through `line` (offset of the line's
+// node 0 along the axis, node stride st), for a tile owning [lo, hi).
+template <int MODE>
+__device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<typename Types<MODE>::M>& mm,
+                                           const Model<typename Types<MODE>::C>& mc, int face, uint32_t line,
+                                           uint32_t st, int n, int lo, int hi)
 {
-    int m = 0;
-    if (((-2 % n) + n) % n == c) m |= 1;
-    if (((-1 % n) + n) % n == c) m |= 2;
-    if (n % n == c) m |= 4;
-    if ((n + 1) % n == c) m |= 8;
-    return m;
+    using S = typename Types<MODE>::S;
+    using C = typename Types<MODE>::C;
+    using M = typename Types<MODE>::M;
+    const int64_t sv = A.g.sv;
+    S* __restrict__ fn = A.fn;
+    const int side = face & 1, kind = A.bc.kind[face], axis = face >> 1;
+    const int g1 = side ? n : -1, g2 = side ? n + 1 : -2;  // wall / first layer, second layer
+    auto at = [&](int c) { return line + (uint32_t)c * st; };
+    C a[NV];
+    if (kind == BC_PERIODIC) {
+        const int gs[2] = {g1, g2};
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int src = ((gs[k] % n) + n) % n;
+            if (src < lo || src >= hi) continue;
+#pragma unroll
+            for (int i = 0; i < NV; i++) a[i] = static_cast<C>((fn + i * sv)[at(src)]);
+            store_node(fn, sv, at(gs[k]), a);
+        }
+        return;
+    }
+    const int i0 = side ? n - 1 : 0, i1 = side ? n - 2 : 1;
+#pragma unroll
+    for (int i = 0; i < NV; i++) a[i] = static_cast<C>((fn + i * sv)[at(i0)]);
+    const Macro<M> q0 = moments<M, C>(a, mm);
+    Macro<M> l1, l2;
+    if (kind == BC_REFLECT) {
+        reflect(q0, axis, l1, l2);
+    } else {  // BC_OUTFLOW
+#pragma unroll
+        for (int i = 0; i < NV; i++) a[i] = static_cast<C>((fn + i * sv)[at(i1)]);
+        const Macro<M> q1 = moments<M, C>(a, mm);
+        extrapolate(q0, q1, l1, l2);
+    }
+    equilibrium<C, M>(l1, mm, mc, a);
+    store_node(fn, sv, at(g1), a);
+    equilibrium<C, M>(l2, mm, mc, a);
+    store_node(fn, sv, at(g2), a);
 }
-__device__ __forceinline__ int wrap_slot(int k, int n) { return k == 0 ? -2 : k == 1 ? -1 : k == 2 ? n : n + 1; }
 
 template <int MODE, int BY>
 __device__ __forceinline__ void step_tile(const StepArgs<MODE>& A, const Model<double>& md,
@@ -357,68 +400,55 @@ __device__ __forceinline__ void step_tile(const StepArgs<MODE>& A, const Model<d
     // sweep, from its new values read back (this thread stored them, so the
     // reads see them); keeping this out of the sweep keeps its register
     // footprint small.  Edges and corners of the layers are never read.
-    // ---- which boundary layers of the new level this node writes
-    const int nxg = g.nx, nyg = g.ny, nzg = g.nz;
-    auto kind_fused = [&](int face, int kind) { return ((A.fused >> face) & 1) && A.bc.kind[face] == kind; };
-    const int pxm = (act && kind_fused(0, BC_PERIODIC)) ? wrap_mask(x, nxg) : 0;
-    const int pym = (act && kind_fused(2, BC_PERIODIC)) ? wrap_mask(y, nyg) : 0;
-    const bool pz = kind_fused(4, BC_PERIODIC);
-    const bool rx_lo = act && x == 0 && kind_fused(0, BC_REFLECT);
-    const bool rx_hi = act && x == nxg - 1 && kind_fused(1, BC_REFLECT);
-    const bool ry_lo = act && y == 0 && kind_fused(2, BC_REFLECT);
-    const bool ry_hi = act && y == nyg - 1 && kind_fused(3, BC_REFLECT);
-    // outflow along x: the node next to the face pairs with its x neighbour,
-    // which sits in the adjacent lane (the host fuses this face only then)
-    const bool ox_lo_t = x0 == 0 && kind_fused(0, BC_OUTFLOW);  // tile-uniform
-    const bool ox_hi_t = x0 <= nxg - 1 && nxg - 1 < x0 + TILE_X && kind_fused(1, BC_OUTFLOW);
-    const bool ox_lo = act && x == 0 && ox_lo_t, ox_hi = act && x == nxg - 1 && ox_hi_t;
-    const bool ox_src = act && ((x == 1 && ox_lo_t) || (x == nxg - 2 && ox_hi_t));
-    const bool xy_bnd = (pxm | pym) || rx_lo || rx_hi || ry_lo || ry_hi || ox_lo || ox_hi || ox_src;
-    const bool ox_t = ox_lo_t || ox_hi_t;
-
-    const bool zlo_t = z0 == 0 && (kind_fused(4, BC_PERIODIC) || kind_fused(4, BC_REFLECT));
-    const bool zhi_t = z1 >= nzg - 1 && (pz || kind_fused(5, BC_REFLECT));
-    if (!(xy_bnd || zlo_t || zhi_t || (pz && z0 < 2)) ) return;
-    for (int z = z0; z < z1; z++) {
-        const int pzm = (pz && (z < 2 || z >= nzg - 2)) ? wrap_mask(z, nzg) : 0;
-        const bool rz_lo = z == 0 && kind_fused(4, BC_REFLECT);
-        const bool rz_hi = z == nzg - 1 && kind_fused(5, BC_REFLECT);
-        if (!(act && (xy_bnd || pzm || rz_lo || rz_hi))) continue;
-        const uint32_t out = col + (uint32_t)z * sz;
-        C o[NV];
+    // ---- boundary layers of the new level (Sec. 4 (2)).  After the sweep,
+    // the tile writes the layers whose source nodes it owns, as dense "line
+    // jobs" spread over all its threads: one job is one line of nodes
+    // perpendicular to a face; it reads back the one or two new nodes next
+    // to the face (written above by this workgroup; the barrier makes them
+    // visible) and writes the two layer nodes.  Edges and corners of the
+    // layers are never read.
+#if !LBM3D_FUSE_LAYERS
+    if (act && hacc) atomicOr(A.health, hacc);
+    return;
+#else
+    const int zc = z1 - z0;
+    const int xe = min(x0 + TILE_X, g.nx), ye = min(y0 + BY, g.ny);
+    bool work[6];
 #pragma unroll
-        for (int i = 0; i < NV; i++) o[i] = static_cast<C>((fn + i * sv)[out]);
+    for (int face = 0; face < 6; face++) {
+        const int axis = face >> 1;
+        const int lo = axis == 0 ? x0 : axis == 1 ? y0 : z0;
+        const int hi = axis == 0 ? xe : axis == 1 ? ye : z1;  // tile owns nodes [lo, hi) along axis
+        const int n = axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz;
+        work[face] = ((A.fused >> face) & 1) && layer_owner(A.bc.kind[face], face & 1, n, lo, hi);
+    }
+    if (!(work[0] || work[1] || work[2] || work[3] || work[4] || work[5])) {
+        if (act && hacc) atomicOr(A.health, hacc);
+        return;
+    }
+    if (act && hacc) atomicOr(A.health, hacc);
+    __syncthreads();
+    const int nthr = TILE_X * BY;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            if ((pxm >> k) & 1) store_node(fn, sv, out + (uint32_t)(wrap_slot(k, nxg) - x), o);
-            if ((pym >> k) & 1) store_node(fn, sv, out + (uint32_t)(wrap_slot(k, nyg) - y) * sy, o);
-            if ((pzm >> k) & 1) store_node(fn, sv, out + (uint32_t)(wrap_slot(k, nzg) - z) * sz, o);
-        }
-        if (rx_lo || rx_hi || ry_lo || ry_hi || rz_lo || rz_hi || ox_lo || ox_hi || ox_src) {
-            const Macro<M> qn = moments<M, C>(o, mm);
-            Macro<M> l1, l2;
-            C e[NV];
-            auto emit = [&](uint32_t off1, uint32_t off2) {
-                equilibrium<C, M>(l1, mm, mc, e);
-                store_node(fn, sv, off1, e);
-                equilibrium<C, M>(l2, mm, mc, e);
-                store_node(fn, sv, off2, e);
-            };
-            if (rx_lo) { reflect(qn, 0, l1, l2); emit(out - 1u, out - 2u); }
-            if (rx_hi) { reflect(qn, 0, l1, l2); emit(out + 1u, out + 2u); }
-            if (ry_lo) { reflect(qn, 1, l1, l2); emit(out - sy, out - 2u * sy); }
-            if (ry_hi) { reflect(qn, 1, l1, l2); emit(out + sy, out + 2u * sy); }
-            if (rz_lo) { reflect(qn, 2, l1, l2); emit(out - sz, out - 2u * sz); }
-            if (rz_hi) { reflect(qn, 2, l1, l2); emit(out + sz, out + 2u * sz); }
-            if (ox_t) {
-                // the outflow pair: the x neighbour's new state from the adjacent lane
-                const Macro<M> qr = shfl_macro(qn, min(tx + 1, TILE_X - 1));
-                const Macro<M> ql = shfl_macro(qn, max(tx - 1, 0));
-                if (ox_lo) { extrapolate(qn, qr, l1, l2); emit(out - 1u, out - 2u); }
-                if (ox_hi) { extrapolate(qn, ql, l1, l2); emit(out + 1u, out + 2u); }
-            }
+    for (int face = 0; face < 6; face++) {
+        if (!work[face]) continue;
+        const int axis = face >> 1;
+        // lines of this face inside the tile: the two other coordinates
+        const int cnt = axis == 0 ? (ye - y0) * zc : axis == 1 ? (xe - x0) * zc : (xe - x0) * (ye - y0);
+        for (int j = threadIdx.x; j < cnt; j += nthr) {
+            int cx = 0, cy = 0, cz = 0;
+            if (axis == 0) { cy = y0 + j % (ye - y0); cz = z0 + j / (ye - y0); }
+            else if (axis == 1) { cx = x0 + j % (xe - x0); cz = z0 + j / (xe - x0); }
+            else { cx = x0 + j % (xe - x0); cy = y0 + j / (xe - x0); }
+            const uint32_t line = (uint32_t)(g.org + (int64_t)cz * g.sz + (int64_t)cy * g.sy + cx);
+            const uint32_t st = axis == 0 ? 1u : axis == 1 ? sy : sz;
+            const int n = axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz;
+            const int lo = axis == 0 ? x0 : axis == 1 ? y0 : z0;
+            const int hi = axis == 0 ? xe : axis == 1 ? ye : z1;
+            layer_line<MODE>(A, mm, mc, face, line, st, n, lo, hi);
         }
     }
+#endif
 }
 
 // Tile order: tiles are numbered with y fastest, then x, then the z chunk,
