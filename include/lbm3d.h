@@ -206,6 +206,11 @@ typedef struct {
  * groups them by precision. */
 int32_t lbm3d_server_create(size_t hbm_budget_bytes, int32_t max_active, lbm3d_server_t* out);
 
+/* Steps per batched tick (default 32): solves submitted during a tick join
+ * at the next one, so a shorter tick admits sooner and a longer one
+ * amortises more launches. */
+int32_t lbm3d_server_set_tick(lbm3d_server_t s, int64_t steps);
+
 /* Queue a solve.  Parameters and the five initial fields are copied; returns
  * immediately with a ticket.  E_NOMEM if the solve alone exceeds the budget;
  * E_INVAL / E_UNSTABLE as lbm3d_create. */

@@ -1,12 +1,330 @@
-// Continuous-batching server (placeholder).
-#include "lbm3d_api_impl.h"
+// Continuous-batching server: a worker thread admits queued solves while
+// their device footprint fits the budget and a slot is free, keeps their
+// state resident on the device, advances all active solves together in
+// batched ticks (one persistent launch per step per precision group), and
+// completes each ticket when its solve has done its steps.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "lbm3d_batch.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Ticket {
+    uint64_t id = 0;
+    lbm3d_params p{};
+    std::vector<double> in[5];
+    std::vector<double> out[5];
+    int64_t nsteps = 0, left = 0;
+    size_t footprint = 0;
+    lbm3d_solver* h = nullptr;
+    enum { QUEUED, ACTIVE, DONE } state = QUEUED;
+    bool cancel = false;
+    int32_t status = LBM3D_OK;
+    uint32_t health = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+}  // namespace
+
+struct lbm3d_server {
+    size_t budget = 0;
+    int max_active = 1;
+    int64_t tick_steps = 32;
+    int device = 0;
+    Clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Ticket*> queue;
+    std::vector<Ticket*> active;
+    std::unordered_map<uint64_t, std::unique_ptr<Ticket>> tickets;
+    size_t used = 0;
+    uint64_t next_id = 1;
+    bool stop = false;
+    bool membership_changed = true;
+    std::thread worker;
+    hipStream_t stream = nullptr;
+    lbm3d::BatchPlan plans[3];  // one per precision
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+    void run();
+    void finish(Ticket* t, int32_t status);
+};
+
+void lbm3d_server::finish(Ticket* t, int32_t status)
+{
+    // caller holds no lock; the solver is only touched by the worker
+    if (t->h) {
+        if (status == LBM3D_OK || status == LBM3D_E_NONFINITE) {
+            const int64_t n = t->h->n;
+            for (int c = 0; c < 5; c++) t->out[c].resize((size_t)n);
+            int32_t rc = lbm3d_moments(t->h, t->out[0].data(), t->out[1].data(), t->out[2].data(),
+                                       t->out[3].data(), t->out[4].data());
+            if (status == LBM3D_OK) status = rc;
+        }
+        uint32_t hw = 0;
+        (void)lbm3d_status(t->h, &hw, nullptr);
+        t->health = hw;
+        (void)lbm3d_destroy(t->h);
+        t->h = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    used -= t->footprint;
+    t->status = status;
+    t->t_done = now();
+    t->state = Ticket::DONE;
+    membership_changed = true;
+    cv_done.notify_all();
+}
+
+void lbm3d_server::run()
+{
+    (void)hipSetDevice(device);
+    for (;;) {
+        std::vector<Ticket*> admit;
+        std::vector<Ticket*> cancelled;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            for (;;) {
+                // queued tickets that were cancelled complete right away
+                for (auto it = queue.begin(); it != queue.end();) {
+                    if ((*it)->cancel) {
+                        Ticket* t = *it;
+                        t->status = LBM3D_E_CANCELLED;
+                        t->t_done = now();
+                        t->state = Ticket::DONE;
+                        cv_done.notify_all();
+                        it = queue.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+                // admission in arrival order: by device footprint and slots
+                while (!queue.empty() && (int)(active.size() + admit.size()) < max_active &&
+                       used + queue.front()->footprint <= budget) {
+                    Ticket* t = queue.front();
+                    queue.pop_front();
+                    used += t->footprint;
+                    admit.push_back(t);
+                }
+                for (Ticket* t : active)
+                    if (t->cancel) cancelled.push_back(t);
+                if (!admit.empty() || !active.empty() || stop) break;
+                cv_work.wait(lk);
+            }
+            if (stop && admit.empty() && active.empty()) return;
+        }
+        // new solves: allocate and initialise outside the lock
+        for (Ticket* t : admit) {
+            lbm3d_solver* h = nullptr;
+            int32_t rc = lbm3d_create(&t->p, &h);
+            if (rc == LBM3D_OK) rc = lbm3d_set_stream(h, stream);
+            if (rc == LBM3D_OK)
+                rc = lbm3d_init(h, t->in[0].data(), t->in[1].data(), t->in[2].data(), t->in[3].data(),
+                                t->in[4].data());
+            for (auto& v : t->in) std::vector<double>().swap(v);
+            t->h = h;
+            if (rc != LBM3D_OK) {
+                finish(t, rc);
+                continue;
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            t->t_admit = now();
+            t->state = Ticket::ACTIVE;
+            active.push_back(t);
+            membership_changed = true;
+        }
+        // evict cancelled solves
+        for (Ticket* t : cancelled) {
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                active.erase(std::find(active.begin(), active.end(), t));
+            }
+            finish(t, LBM3D_E_CANCELLED);
+        }
+        std::vector<Ticket*> act;
+        bool rebuild;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            act = active;
+            rebuild = membership_changed;
+            membership_changed = false;
+        }
+        if (act.empty()) continue;
+        // one tick: every precision group advances by the same number of
+        // steps, at most tick_steps and at most what its members still need
+        int32_t err = LBM3D_OK;
+        for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++) {
+            std::vector<lbm3d_solver*> members;
+            int64_t k = tick_steps;
+            for (Ticket* t : act)
+                if (t->h->mode == mode) {
+                    members.push_back(t->h);
+                    k = std::min(k, t->left);
+                }
+            if (members.empty() || k <= 0) continue;
+            if (rebuild || plans[mode].ntiles() == 0) err = plans[mode].build(members, stream);
+            if (err == LBM3D_OK) err = plans[mode].run(k, stream);
+            if (err == LBM3D_OK)
+                for (Ticket* t : act)
+                    if (t->h->mode == mode) t->left -= k;
+        }
+        if (err == LBM3D_OK && hipStreamSynchronize(stream) != hipSuccess) err = LBM3D_E_DEVICE;
+        // completions (and every active solve if the tick failed)
+        for (Ticket* t : act) {
+            if (err == LBM3D_OK && t->left > 0) continue;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                active.erase(std::find(active.begin(), active.end(), t));
+            }
+            uint32_t hw = 0;
+            if (err == LBM3D_OK) (void)lbm3d_status(t->h, &hw, nullptr);
+            finish(t, err != LBM3D_OK ? err : ((hw & LBM3D_HEALTH_NONFINITE) ? LBM3D_E_NONFINITE : LBM3D_OK));
+        }
+    }
+}
 
 extern "C" {
-int32_t lbm3d_server_create(size_t, int32_t, lbm3d_server_t* out) { if (out) *out = nullptr; return LBM3D_E_STATE; }
-int32_t lbm3d_server_submit(lbm3d_server_t, const lbm3d_params*, const double*, const double*, const double*,
-                            const double*, const double*, int64_t, uint64_t*) { return LBM3D_E_STATE; }
-int32_t lbm3d_server_poll(lbm3d_server_t, uint64_t, int32_t*) { return LBM3D_E_STATE; }
-int32_t lbm3d_server_wait(lbm3d_server_t, uint64_t, double*, double*, double*, double*, double*, lbm3d_timing*) { return LBM3D_E_STATE; }
-int32_t lbm3d_server_cancel(lbm3d_server_t, uint64_t) { return LBM3D_E_STATE; }
-int32_t lbm3d_server_destroy(lbm3d_server_t) { return LBM3D_OK; }
+
+int32_t lbm3d_server_create(size_t hbm_budget_bytes, int32_t max_active, lbm3d_server_t* out)
+{
+    if (!out || max_active < 1 || hbm_budget_bytes == 0) return LBM3D_E_INVAL;
+    *out = nullptr;
+    lbm3d_server* s = new (std::nothrow) lbm3d_server();
+    if (!s) return LBM3D_E_NOMEM;
+    s->budget = hbm_budget_bytes;
+    s->max_active = max_active;
+    s->t0 = Clock::now();
+    if (hipGetDevice(&s->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return LBM3D_E_DEVICE;
+    }
+    try {
+        s->worker = std::thread([s] { s->run(); });
+    } catch (...) {
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        return LBM3D_E_NOMEM;
+    }
+    *out = s;
+    return LBM3D_OK;
 }
+
+int32_t lbm3d_server_set_tick(lbm3d_server_t s, int64_t steps)
+{
+    if (!s || steps < 1) return LBM3D_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->tick_steps = steps;
+    return LBM3D_OK;
+}
+
+int32_t lbm3d_server_submit(lbm3d_server_t s, const lbm3d_params* p, const double* rho, const double* ux,
+                            const double* uy, const double* uz, const double* pr, int64_t nsteps,
+                            uint64_t* ticket)
+{
+    if (!s || !p || !rho || !ux || !uy || !uz || !pr || !ticket || nsteps < 0) return LBM3D_E_INVAL;
+    size_t fp = 0;
+    int32_t rc = lbm3d_footprint(p, &fp);
+    if (rc) return rc;
+    if (fp > s->budget) return LBM3D_E_NOMEM;
+    const size_t n = (size_t)p->nx * p->ny * p->nz;
+    for (size_t k = 0; k < n; k++)
+        if (!(rho[k] > 0.0) || !(pr[k] > 0.0)) return LBM3D_E_INVAL;
+    std::unique_ptr<Ticket> t(new (std::nothrow) Ticket());
+    if (!t) return LBM3D_E_NOMEM;
+    t->p = *p;
+    const double* src[5] = {rho, ux, uy, uz, pr};
+    try {
+        for (int c = 0; c < 5; c++) t->in[c].assign(src[c], src[c] + n);
+    } catch (...) {
+        return LBM3D_E_NOMEM;
+    }
+    t->nsteps = t->left = nsteps;
+    t->footprint = fp;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return LBM3D_E_STATE;
+    t->id = s->next_id++;
+    t->t_submit = s->now();
+    *ticket = t->id;
+    s->queue.push_back(t.get());
+    s->tickets[t->id] = std::move(t);
+    s->cv_work.notify_one();
+    return LBM3D_OK;
+}
+
+int32_t lbm3d_server_poll(lbm3d_server_t s, uint64_t ticket, int32_t* done)
+{
+    if (!s || !done) return LBM3D_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return LBM3D_E_NOTFOUND;
+    *done = it->second->state == Ticket::DONE ? 1 : 0;
+    return LBM3D_OK;
+}
+
+int32_t lbm3d_server_wait(lbm3d_server_t s, uint64_t ticket, double* rho, double* ux, double* uy, double* uz,
+                          double* p, lbm3d_timing* tm)
+{
+    if (!s) return LBM3D_E_INVAL;
+    std::unique_ptr<Ticket> t;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->tickets.find(ticket);
+        if (it == s->tickets.end()) return LBM3D_E_NOTFOUND;
+        Ticket* tp = it->second.get();
+        s->cv_done.wait(lk, [tp] { return tp->state == Ticket::DONE; });
+        t = std::move(it->second);
+        s->tickets.erase(it);
+    }
+    double* dst[5] = {rho, ux, uy, uz, p};
+    for (int c = 0; c < 5; c++)
+        if (dst[c] && !t->out[c].empty()) std::memcpy(dst[c], t->out[c].data(), t->out[c].size() * sizeof(double));
+    if (tm) {
+        tm->t_submit = t->t_submit;
+        tm->t_admit = t->t_admit;
+        tm->t_done = t->t_done;
+        tm->steps = t->nsteps - t->left;
+        tm->health = t->health;
+    }
+    return t->status;
+}
+
+int32_t lbm3d_server_cancel(lbm3d_server_t s, uint64_t ticket)
+{
+    if (!s) return LBM3D_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return LBM3D_E_NOTFOUND;
+    it->second->cancel = true;
+    s->cv_work.notify_one();
+    return LBM3D_OK;
+}
+
+int32_t lbm3d_server_destroy(lbm3d_server_t s)
+{
+    if (!s) return LBM3D_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (auto& kv : s->tickets) kv.second->cancel = true;
+        s->cv_work.notify_one();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamDestroy(s->stream);
+    delete s;
+    return LBM3D_OK;
+}
+
+}  // extern "C"

@@ -81,6 +81,7 @@ def _load():
         "lbm3d_set_f": (I32, [P, P, SZ]),
         "lbm3d_batch_step": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(I64)]),
         "lbm3d_server_create": (I32, [SZ, I32, ctypes.POINTER(P)]),
+        "lbm3d_server_set_tick": (I32, [P, I64]),
         "lbm3d_server_submit": (I32, [P, PP, D, D, D, D, D, I64, ctypes.POINTER(U64)]),
         "lbm3d_server_poll": (I32, [P, U64, ctypes.POINTER(I32)]),
         "lbm3d_server_wait": (I32, [P, U64, D, D, D, D, D, ctypes.POINTER(lbm3d_timing)]),
@@ -261,6 +262,10 @@ def lbm3d_server_create(hbm_budget_bytes: int, max_active: int):
     return s
 
 
+def lbm3d_server_set_tick(s, steps: int):
+    _check(_lib.lbm3d_server_set_tick(s, int(steps)), "lbm3d_server_set_tick")
+
+
 def lbm3d_server_submit(s, params, fields, nsteps: int) -> int:
     p = _params(params)
     n = p.nx * p.ny * p.nz
@@ -358,3 +363,42 @@ class Solver:
 
     def set_f(self, f):
         lbm3d_set_f(self.h, f)
+
+
+class Server:
+    """Continuous-batching server: ``Server(budget_bytes, max_active)``;
+    ``submit(params, fields, nsteps) -> ticket``; ``wait(ticket, shape)``."""
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int, tick_steps: int = None):
+        self.s = lbm3d_server_create(hbm_budget_bytes, max_active)
+        if tick_steps is not None:
+            lbm3d_server_set_tick(self.s, tick_steps)
+
+    def submit(self, params, fields, nsteps: int) -> int:
+        return lbm3d_server_submit(self.s, params, fields, nsteps)
+
+    def poll(self, ticket: int) -> bool:
+        return lbm3d_server_poll(self.s, ticket)
+
+    def wait(self, ticket: int, shape):
+        return lbm3d_server_wait(self.s, ticket, shape)
+
+    def cancel(self, ticket: int):
+        lbm3d_server_cancel(self.s, ticket)
+
+    def close(self):
+        if self.s is not None and self.s.value:
+            lbm3d_server_destroy(self.s)
+        self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
