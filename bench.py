@@ -1,29 +1,78 @@
 #!/usr/bin/env python3
-"""Benchmark of the fused FD-LB time step on one MI355X.
+"""Benchmark of the 3D FD-LB solver on one MI355X.  Prints one JSON line.
 
-Workload: the 256x128x128 shock-bubble problem (planar shock of seeded Mach
-number into quiescent gas, a bubble or droplet of seeded density ratio,
-inflow/outflow in x, reflecting walls in y and z), FP32 storage and
-arithmetic with the temperature recovered in FP64, synthetic seeded input.
-A step is one time step of the whole grid: the fused moments + equilibrium +
-NND convection + dissipation + BGK update kernel and the boundary-layer
-refresh.  Prints one JSON line.
+Headline (`value`): MLUPS of the time step on the 256x128x128 shock-bubble
+problem (planar shock of seeded Mach number into quiescent gas, a bubble or
+droplet of seeded density ratio, inflow/outflow in x, reflecting walls in y
+and z), FP32 storage and arithmetic with the temperature recovered in FP64,
+synthetic seeded input already resident on the device.  A step is one time
+step of the whole grid: the fused moments + equilibrium + NND convection +
+dissipation + BGK update kernel and the boundary-layer kernel, replayed from
+a captured graph.
+
+Beside it:
+  roofline      the fused step kernel's algorithmic HBM rate (15 reads + 15
+                writes of f per node) over its mean launch time, measured with
+                HIP events around each launch, against the 8 TB/s peak;
+                `traffic` is the counter-measured HBM bytes per launch from
+                the committed rocprofv3 summary when it was taken on this
+                kernel source, else null;
+  batch         64 solves of uneven size, 500 steps each, in one persistent
+                launch per step vs the same solves stepped one after another;
+  serving       an open Poisson stream of mixed solves through the
+                continuous-batching server vs the plain one-at-a-time FP64
+                loop on the same arrival times: solves/s, p50/p99 time to
+                solution, and the served results' error against FP64;
+  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S]
+                  [--no-batch] [--no-serve] [--no-cpu-baseline] [--copy-check]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import threading
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, vendor figure
 BYTES_PER_SITE = {"fp64": 240, "fp32": 120, "fp32_t64": 120}  # 15 reads + 15 writes of f
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_hbm_traffic.txt")
+KERNEL_SOURCES = ["lbm3d_tile.h", "lbm3d_model.h", "lbm3d_device.hip", "lbm3d_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1010_4135_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision: str):
+    """Counter-measured HBM bytes per step-kernel launch from the committed
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash() or kv.get("precision") != precision:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(case, steps: int = 3):
@@ -38,8 +87,108 @@ def cpu_baseline(case, steps: int = 3):
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": case.sites * steps / dt / 1e6, "unit": "MLUPS", "cores": used, "kind": "oracle",
+    return {"value": round(case.sites * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": used, "kind": "oracle",
             "sample": f"{case.grid[0]}x{case.grid[1]}x{case.grid[2]} full grid, {steps} steps after 1 warm-up, FP64"}
+
+
+def batch_bench(lbm3d, inputs, seed: int, count: int = 64, steps: int = 500):
+    """64 uneven solves: one persistent launch per step vs one solve at a time."""
+    cases = inputs.batch_cases(seed, count=count, steps=steps, precision="fp32_t64")
+    sites = sum(c.sites for c in cases)
+
+    def fresh():
+        out = []
+        for c in cases:
+            s = lbm3d.Solver(c.params)
+            s.init(*c.fields)
+            out.append(s)
+        return out
+
+    solvers = fresh()
+    lbm3d.lbm3d_batch_step([s.h for s in solvers], [1] * count)  # warm-up (plan, graph, code)
+    t0 = time.perf_counter()
+    lbm3d.lbm3d_batch_step([s.h for s in solvers], [steps] * count)
+    t_batch = time.perf_counter() - t0
+    f_batch = [s.get_f() for s in solvers[:4]]
+    for s in solvers:
+        s.close()
+    solvers = fresh()
+    for s in solvers:
+        s.step(1)
+        s.sync()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps)
+        s.sync()
+    t_seq = time.perf_counter() - t0
+    same = all(np.array_equal(a, s.get_f()) for a, s in zip(f_batch, solvers[:4]))
+    for s in solvers:
+        s.close()
+    return {"solves": count, "steps_each": steps, "sites_total": sites, "precision": "fp32_t64",
+            "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
+            "batched_mlups": round(sites * steps / t_batch / 1e6, 1),
+            "sequential_mlups": round(sites * steps / t_seq / 1e6, 1),
+            "speedup": round(t_seq / t_batch, 3), "first4_bitwise_equal_alone": bool(same)}
+
+
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def serve_bench(lbm3d, inputs, metrics, seed: int, count: int = 24):
+    """Open Poisson stream: served (continuous batching, FP32 + FP64 T) vs the
+    plain one-at-a-time FP64 loop on the same arrival times."""
+    # capacity of the served path with everything submitted at once sets the rate
+    probe = inputs.serve_trace(seed + 1, count=count, rate=1e9)
+    budget = int(200e9)
+
+    def run_served(trace):
+        with lbm3d.Server(budget, 64, tick_steps=32) as srv:
+            t_start = time.perf_counter()
+            tickets = []
+            for t_arr, c in trace:
+                delay = t_arr - (time.perf_counter() - t_start)
+                if delay > 0:
+                    time.sleep(delay)
+                tickets.append((srv.submit(c.params, c.fields, c.steps), c))
+            out, lat = [], []
+            for t, c in tickets:
+                nx, ny, nz = c.grid
+                rc, fields, tm = srv.wait(t, (nz, ny, nx))
+                out.append(fields)
+                lat.append(tm["t_done"] - tm["t_submit"])
+            wall = time.perf_counter() - t_start
+        return out, lat, wall
+
+    _, _, w = run_served(probe)
+    capacity = count / w
+    rate = 0.8 * capacity
+    trace = inputs.serve_trace(seed, count=count, rate=rate)
+    served, lat_s, wall_s = run_served(trace)
+
+    # baseline: each request alone in FP64, in arrival order
+    base, lat_b = [], []
+    t_start = time.perf_counter()
+    for t_arr, c in trace:
+        now = time.perf_counter() - t_start
+        if t_arr > now:
+            time.sleep(t_arr - now)
+        prm = dict(c.params, precision="fp64")
+        s = lbm3d.Solver(prm)
+        s.init(*c.fields)
+        s.step(c.steps)
+        base.append(s.moments())
+        s.close()
+        lat_b.append(time.perf_counter() - t_start - t_arr)
+    wall_b = time.perf_counter() - t_start
+    err = max(metrics.max_rel_l1(a, b) for a, b in zip(served, base))
+    return {"requests": count, "arrival_rate_per_s": round(rate, 3), "served_precision": "fp32_t64",
+            "baseline": "one solve at a time, FP64, arrival order",
+            "served_solves_per_s": round(count / wall_s, 3), "baseline_solves_per_s": round(count / wall_b, 3),
+            "throughput_ratio": round(wall_b / wall_s, 3),
+            "served_p50_s": round(_pct(lat_s, 50), 4), "served_p99_s": round(_pct(lat_s, 99), 4),
+            "baseline_p50_s": round(_pct(lat_b, 50), 4), "baseline_p99_s": round(_pct(lat_b, 99), 4),
+            "max_rel_l1_served_vs_fp64": float(f"{err:.3e}")}
 
 
 def main():
@@ -50,13 +199,17 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default="fp32_t64", choices=["fp64", "fp32", "fp32_t64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-check", action="store_true",
+                    help="also run the checkpoint pack (a plain copy of 15 x nodes elements) for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not implemented", file=sys.stderr)
         sys.exit(2)
 
-    from paper_1010_4135_amd import inputs, lbm3d
+    from paper_1010_4135_amd import inputs, lbm3d, metrics
 
     case = inputs.shock_bubble(args.seed, precision=args.precision)
     nx, ny, nz = case.grid
@@ -74,10 +227,14 @@ def main():
     # per-launch duration of the fused step kernel (events around each launch)
     _, kernel_ms = s.step_profiled(min(200, args.steps))
     health, done = s.status()
+    if args.copy_check:
+        for _ in range(3):
+            s.get_f()
+    by, tz = s.get_tile()
     bps = BYTES_PER_SITE[args.precision]
     achieved = case.sites * bps / (kernel_ms / 1e3) / 1e9
     out = {
-        "metric": "MLUPS (lattice-site updates per second, 1e6) of the fused FD-LB step",
+        "metric": "MLUPS (lattice-site updates per second, 1e6) of the FD-LB time step",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -87,23 +244,27 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision != "fp64" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"shock_bubble {nx}x{ny}x{nz}, {args.precision} (FP32 f, FP64 temperature recovery)"
-                        if args.precision == "fp32_t64" else f"shock_bubble {nx}x{ny}x{nz}, {args.precision}",
+            "workload": f"shock_bubble {nx}x{ny}x{nz}, {args.precision}" +
+                        (" (FP32 f, FP64 temperature recovery)" if args.precision == "fp32_t64" else ""),
             "grid": [nx, ny, nz], "precision": args.precision, "seed": args.seed,
             "mach": round(case.meta["mach"], 4), "density_ratio": round(case.meta["ratio"], 4),
-            "wall_s_timed_region": round(wall, 4), "health": health, "steps_done": done,
+            "tile": [64, by, tz], "wall_s_timed_region": round(wall, 4), "health": health, "steps_done": done,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-            "kernel": "k_step", "kernel_ms": round(kernel_ms, 5),
-            "bytes_per_site": bps,
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.precision),
+            "kernel": "k_step_tiled", "kernel_ms": round(kernel_ms, 5), "bytes_per_site": bps,
+            "sites_per_launch": case.sites,
         },
     }
     s.close()
+    if not args.no_batch:
+        out["batch"] = batch_bench(lbm3d, inputs, args.seed)
+    if not args.no_serve:
+        out["serving"] = serve_bench(lbm3d, inputs, metrics, args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)
