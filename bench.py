@@ -34,6 +34,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import threading
 import time
@@ -50,10 +51,15 @@ KERNEL_SOURCES = ["lbm3d_tile.h", "lbm3d_model.h", "lbm3d_device.hip", "lbm3d_in
 
 
 def kernel_source_hash() -> str:
+    """Hash of the step kernel's code: comments and whitespace are dropped,
+    so only a change of the code itself invalidates the counter figures."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1010_4135_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1010_4135_amd", "csrc", name)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update("".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -18,9 +18,9 @@
 //   - moments, equilibrium, NND convection in x, y, z, dissipation and the
 //     BGK forward-Euler update are evaluated in registers and each new f is
 //     written once;
-//   - tiles next to a periodic, reflecting or extrapolating face then write
-//     the boundary layers of the new level themselves, so no second kernel
-//     is needed for them.
+//   - the boundary layers of the new level are written by a separate,
+//     light launch (one thread per boundary line); a build option moves
+//     the periodic and reflecting ones into the tiles next to the face.
 // Per node, the arithmetic is the same sequence of operations as a direct
 // evaluation of the stencil, so results do not depend on the tile shape.
 #pragma once
@@ -395,11 +395,6 @@ __device__ __forceinline__ void step_tile(const StepArgs<MODE>& A, const Model<d
     }
     if (act && hacc) atomicOr(A.health, hacc);
 
-    // ---- boundary layers of the new level (Sec. 4 (2)).  The node next to
-    // each periodic, reflecting or (x) outflow face writes them after the
-    // sweep, from its new values read back (this thread stored them, so the
-    // reads see them); keeping this out of the sweep keeps its register
-    // footprint small.  Edges and corners of the layers are never read.
     // ---- boundary layers of the new level (Sec. 4 (2)).  After the sweep,
     // the tile writes the layers whose source nodes it owns, as dense "line
     // jobs" spread over all its threads: one job is one line of nodes

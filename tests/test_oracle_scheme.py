@@ -289,8 +289,8 @@ def _tube_error(left, right, nx, dx, steps, model, ny=1):
 
 @pytest.mark.parametrize("seed", [0, 4])
 def test_shock_tube_converges_to_exact_riemann(seed):
-    """Config-0 style draws at fixed t = 0.005: relative L1 error per field
-    falls under refinement dx = 1/128 -> 1/256 -> 1/512."""
+    """Seeded quasi-1D Riemann draws at fixed t = 0.005: relative L1 error per
+    field falls under refinement dx = 1/128 -> 1/256 -> 1/512."""
     case = inputs.riemann_1d(seed)
     L, R = case.meta["left"], case.meta["right"]
     errs = []
