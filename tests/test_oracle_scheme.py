@@ -13,6 +13,8 @@
 - Reflecting walls are mirror symmetric.
 - Shock tubes converge to the exact Riemann solution of the Euler equations
   (Sec. 4 (1)); small waves travel at the sound speed sqrt(gamma T).
+- A one-node impulse on a uniform equilibrium gives, after one step, the
+  closed-form dissipation, upwind flux and relaxation of Sec. 3.
 """
 import json
 import math
@@ -389,3 +391,55 @@ def test_exact_riemann_solver_pins():
     xi = np.linspace(-1.1, 0.0, 50)
     r, u, p = riemann.sample(L, R, 1.4, xi)
     np.testing.assert_allclose(p / r ** 1.4, 1.0, rtol=1e-12)
+
+
+@pytest.mark.parametrize("i", range(15))
+def test_single_node_impulse_response(i):
+    """One step from a uniform equilibrium in which one distribution f_i is
+    raised by eps at one node.  Every other node is in equilibrium with a
+    uniform neighbourhood, so its BGK term vanishes and the step reduces to
+    closed forms of Sec. 3, Eqs. (nnd), (lp), (fi1):
+      - a face neighbour J = I +- e_a gains dt lambda_i eps / dx^2 from the
+        dissipation (lambda = c1 dx for the rest velocity, c1 dx / 10 for
+        the axis velocities, 0 for the diagonal ones);
+      - the downwind neighbour along each axis with v_ia != 0 gains
+        dt |v_ia| eps / dx from the NND flux (minmod of a one-sided jump and
+        zero is zero, so the upwind side and nodes two away see nothing);
+      - node I itself loses 6 dt lambda_i eps / dx^2 + dt sum_a |v_ia| eps / dx
+        and relaxes towards the equilibrium of its own moments by dt / tau;
+      - every other distribution and node is unchanged."""
+    prm = inputs.make_params((9, 9, 9), (0,) * 6, tau=2e-5)
+    c1, c2, eta0, gamma = prm["c1"], prm["c2"], prm["eta0"], prm["gamma"]
+    dt, dx, tau = prm["dt"], prm["dx"], prm["tau"]
+    v, _ = oracle.velocities(c1, c2, eta0)
+    lam = [c1 * dx] + [c1 * dx / 10.0] * 6 + [0.0] * 8
+    shape = (9, 9, 9)
+    rho, ux, uy, uz, T = 1.1, 0.3, -0.2, 0.1, 1.2
+    o = oracle.Oracle(prm)
+    o.init(*(np.full(shape, a) for a in (rho, ux, uy, uz, rho * T)))
+    f0 = o.get_f()
+    I = np.array([4, 4, 4])  # (z, y, x)
+    eps = 0.01 * f0[(i,) + tuple(I)]
+    f = f0.copy()
+    f[(i,) + tuple(I)] += eps
+    o.set_f(f)
+    o.step(1)
+    got = o.get_f()
+
+    exp = f0.copy()
+    for a in range(3):               # axis a: x, y, z
+        e = np.zeros(3, dtype=int)
+        e[2 - a] = 1                 # (z, y, x) index offset of +e_a
+        for s in (1, -1):
+            J = tuple(I + s * e)
+            exp[(i,) + J] += dt * lam[i] * eps / dx ** 2
+            if v[i, a] * s > 0:
+                exp[(i,) + J] += dt * abs(v[i, a]) * eps / dx
+    fI = f[(slice(None),) + tuple(I)]
+    q = oracle.moments_of(c1, c2, eta0, gamma, fI)
+    feq = oracle.equilibrium(c1, c2, eta0, gamma, *q)
+    exp[(slice(None),) + tuple(I)] = fI - dt / tau * (fI - feq)
+    exp[(i,) + tuple(I)] -= 6 * dt * lam[i] * eps / dx ** 2 + dt * np.abs(v[i]).sum() * eps / dx
+    np.testing.assert_allclose(got, exp, rtol=0, atol=1e-13 * np.abs(f0).max())
+    # the response is not negligible against that tolerance
+    assert np.abs(got - f0).max() > 1e-6 * np.abs(f0).max()
