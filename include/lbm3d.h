@@ -185,7 +185,9 @@ int32_t lbm3d_set_f(lbm3d_t h, const void* host, size_t bytes);
  * of a persistent kernel over a packed queue of tiles from every solve that
  * still has steps to do; groups of steps are replayed from captured HIP
  * graphs.  Results are bitwise identical to stepping each solve alone.
- * Blocking.  E_INVAL for mixed precisions, duplicate handles, count < 1. */
+ * Blocking.  E_INVAL for mixed precisions, duplicate handles, count < 1,
+ * or a solve whose velocity plane (about nx*ny*nz elements) reaches 2 GiB:
+ * the batched kernel addresses a plane with 32-bit offsets. */
 int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* nsteps);
 
 /* ------------------------------------------------------------- serving --- */
@@ -213,7 +215,8 @@ int32_t lbm3d_server_set_tick(lbm3d_server_t s, int64_t steps);
 
 /* Queue a solve.  Parameters and the five initial fields are copied; returns
  * immediately with a ticket.  E_NOMEM if the solve alone exceeds the budget;
- * E_INVAL / E_UNSTABLE as lbm3d_create. */
+ * E_INVAL / E_UNSTABLE as lbm3d_create, E_INVAL also for a solve the
+ * batched kernel cannot take (see lbm3d_batch_step). */
 int32_t lbm3d_server_submit(lbm3d_server_t s, const lbm3d_params* p, const double* rho,
                             const double* ux, const double* uy, const double* uz,
                             const double* pr, int64_t nsteps, uint64_t* ticket);

@@ -10,6 +10,13 @@
 #include <new>
 #include <vector>
 
+// Build-time layout knob: 1 = one cache line of padding per row shared by
+// the layer nodes of two rows; 0 = the layers of each row in lines of
+// their own.
+#ifndef LBM3D_SHARED_GHOST_LINE
+#define LBM3D_SHARED_GHOST_LINE 1
+#endif
+
 using namespace lbm3d;
 
 namespace lbm3d {
@@ -95,6 +102,8 @@ Model<double> make_model(const lbm3d_params* p)
     const bool diss = !(p->flags & LBM3D_NO_DISSIPATION);
     m.k_lap0 = diss ? c1 * p->dx * p->dt / (p->dx * p->dx) : 0.0;
     m.k_lap1 = diss ? c1 * p->dx / 10.0 * p->dt / (p->dx * p->dx) : 0.0;
+    m.a1 = m.k_adv * m.c1;
+    m.ad = m.k_adv * m.k;
     return m;
 }
 
@@ -121,7 +130,14 @@ Grid make_grid(const lbm3d_params* p)
     g.ny = p->ny;
     g.nz = p->nz;
     const int64_t ox = line;
+#if LBM3D_SHARED_GHOST_LINE
+    // one cache line of padding per row, holding the two right layer nodes
+    // of the row (its first elements) and the two left layer nodes of the
+    // next row (its last elements); interior rows start on a line
+    const int64_t mx = (p->nx + line - 1) / line * line + line;
+#else
     const int64_t mx = ((ox + p->nx + NG) + line - 1) / line * line;
+#endif
     const int64_t my = p->ny + 2 * NG;
     const int64_t mz = p->nz + 2 * NG;
     g.sy = mx;
@@ -131,10 +147,11 @@ Grid make_grid(const lbm3d_params* p)
     const int64_t blk = 256 / (int64_t)elem_size(p->precision);
     // one spare element past the plane: the sink of the step kernel's
     // stores from lanes outside the grid
-    int64_t sv = (g.sz * mz + 1 + blk - 1) / blk;
+    // (the right layer nodes of the last row reach two elements past sz * mz)
+    int64_t sv = (g.sz * mz + 2 * line + blk - 1) / blk;
     if ((sv & 1) == 0) sv += 1;
     g.sv = sv * blk;
-    g.sink = g.sz * mz;
+    g.sink = g.sz * mz + line;
     g.org = NG * g.sz + NG * g.sy + ox;
     return g;
 }
@@ -223,9 +240,10 @@ int32_t solver_create(const lbm3d_params* p, lbm3d_solver** out)
 // boundary layers of the new level.
 static hipError_t enqueue_one(lbm3d_solver* h, int cur, hipStream_t s)
 {
-    hipError_t e = launch_step(h->mode, h->g, h->bc, h->tile, h->md, h->mf, h->f[cur], h->f[cur ^ 1], h->health, s);
+    hipError_t e = launch_step(h->mode, h->g, h->bc, h->tile, h->md, h->mf, h->p.inflow, h->f[cur], h->f[cur ^ 1],
+                               h->health, s);
     if (e != hipSuccess) return e;
-    const uint32_t rest = ghost_faces(h->bc, fused_faces(h->g, h->bc, h->tile));
+    const uint32_t rest = ghost_faces(h->g, h->bc, h->tile.by != 0);
     if (!rest) return hipSuccess;
     return launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[cur ^ 1], s, rest);
 }
@@ -391,9 +409,10 @@ int32_t lbm3d_step_profiled(lbm3d_t h, int64_t nsteps, double* total_ms, double*
         const int c = h->cur;
         e = hipEventRecord(ev[2 * k], s);
         if (e == hipSuccess)
-            e = launch_step(h->mode, h->g, h->bc, h->tile, h->md, h->mf, h->f[c], h->f[c ^ 1], h->health, s);
+            e = launch_step(h->mode, h->g, h->bc, h->tile, h->md, h->mf, h->p.inflow, h->f[c], h->f[c ^ 1],
+                            h->health, s);
         if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], s);
-        const uint32_t rest = ghost_faces(h->bc, fused_faces(h->g, h->bc, h->tile));
+        const uint32_t rest = ghost_faces(h->g, h->bc, h->tile.by != 0);
         if (e == hipSuccess && rest)
             e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[c ^ 1], s, rest);
         if (e == hipSuccess) {
@@ -424,7 +443,7 @@ int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz)
     TileCfg t;
     t.by = by;
     t.tz = tz;
-    if (!tile_supported(h->mode, t)) return LBM3D_E_INVAL;
+    if (!tile_supported(h->mode, h->g, t)) return LBM3D_E_INVAL;
     HIPCHK(hipStreamSynchronize(h->stream));
     for (int k = 0; k < 2; k++)
         if (h->graph_exec[k]) {
@@ -432,6 +451,12 @@ int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz)
             h->graph_exec[k] = nullptr;
         }
     h->tile = t;
+    // the layers a tiled step forms itself are not kept in memory: refresh
+    // them all, so any launch shape can take over
+    if (h->initialised) {
+        HIPCHK(launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, true, h->f[h->cur], h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
     return LBM3D_OK;
 }
 

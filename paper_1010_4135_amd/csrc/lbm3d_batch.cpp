@@ -42,7 +42,7 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     by_ = mode_ == LBM3D_FP64 ? 4 : 8;
     tz_ = 8;
 
-    // packed tile list: each solve's tiles in (z chunk, x, y) order, split
+    // packed tile list: each solve's tiles in (z chunk, y, x) order, split
     // into eight contiguous runs interleaved so that run c lands on XCD c
     // (workgroup b runs tiles b, b + G, ... with G a multiple of 8)
     std::vector<BatchTile> order;
@@ -51,27 +51,24 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     cur0_.assign(members.size(), 0);
     for (size_t k = 0; k < members.size(); k++) {
         lbm3d_solver* h = members[k];
-        TileCfg tc;
-        tc.by = by_;
-        tc.tz = tz_;
         BatchSolve& d = table[k];
         std::memset(&d, 0, sizeof(d));
         d.g = h->g;
         d.bc = h->bc;
-        d.fused = fused_faces(h->g, h->bc, tc);
         d.cur0 = h->cur;
+        x_fixed_states(h->p.inflow, d.xin);
         d.f[0] = h->f[0];
         d.f[1] = h->f[1];
         d.health = h->health;
         d.md = h->md;
         d.mf = h->mf;
-        ghost_rest_[k] = ghost_faces(h->bc, d.fused);
+        ghost_rest_[k] = ghost_faces(h->g, h->bc, true);
         cur0_[k] = h->cur;
         const int ntx = (h->g.nx + TILE_X - 1) / TILE_X;
         const int nty = (h->g.ny + by_ - 1) / by_;
         for (int z0 = 0; z0 < h->g.nz; z0 += tz_)
-            for (int tx = 0; tx < ntx; tx++)
-                for (int ty = 0; ty < nty; ty++) {
+            for (int ty = 0; ty < nty; ty++)
+                for (int tx = 0; tx < ntx; tx++) {
                     BatchTile t;
                     t.solve = (int32_t)k;
                     t.txi = (int16_t)tx;
@@ -180,6 +177,12 @@ int32_t BatchPlan::run(int64_t k, hipStream_t s)
     for (lbm3d_solver* h : members_) {
         h->steps += k;
         if (k & 1) h->cur ^= 1;
+        // a member that steps alone untiled reads every layer from memory:
+        // refresh the ones the tiled batch kernel formed itself
+        if (h->tile.by == 0) {
+            hipError_t e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[h->cur], s);
+            if (e != hipSuccess) return herr(e);
+        }
     }
     return LBM3D_OK;
 }
@@ -197,6 +200,7 @@ extern "C" int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* n
         if (!hs[k] || nsteps[k] < 0 || !seen.insert(hs[k]).second) return LBM3D_E_INVAL;
         if (!hs[k]->initialised) return LBM3D_E_STATE;
         if (hs[k]->mode != hs[0]->mode) return LBM3D_E_INVAL;
+        if (!lbm3d::tiled_fits(hs[k]->mode, hs[k]->g)) return LBM3D_E_INVAL;
     }
     hipStream_t s = hs[0]->stream;
     // work already queued on the other solves' streams precedes the batch

@@ -13,41 +13,36 @@ namespace lbm3d {
 //               - dt/tau (f_i - f_i^eq) + lambda_i dt/dx^2 sum_a (f_{I+1} - 2 f_I + f_{I-1})
 // reading every term at level n (forward Euler, Eq. (fi1)).  The boundary
 // layers of f^n hold valid values, so every neighbour load is in bounds.
+// This one-node-per-thread kernel and the tiled one evaluate the same
+// operations per node (node_update and the NND helpers), so they agree
+// bitwise.
 template <int I, typename S, typename C>
 __device__ __forceinline__ void update_one(const S* __restrict__ fi, S* __restrict__ fo,
                                            int64_t sy, int64_t sz, C f0, C feq,
                                            const Model<C>& m)
 {
-    constexpr int SX = vsign(I, 0), SY = vsign(I, 1), SZ = vsign(I, 2), G = vgroup(I);
-    const C vm = (G == 1) ? m.c1 : m.k;
-    C conv = C(0);
+    constexpr int SG[3] = {vsign(I, 0), vsign(I, 1), vsign(I, 2)};
+    constexpr int G = vgroup(I);
     const int64_t st[3] = {1, sy, sz};
-    constexpr int SG[3] = {SX, SY, SZ};
+    C D[3] = {C(0), C(0), C(0)}, L[3] = {C(0), C(0), C(0)};
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        if (SG[a] == 0) continue;
         const int64_t s = st[a];
-        const C fm1 = static_cast<C>(fi[-s]);
-        const C fp1 = static_cast<C>(fi[s]);
-        C d;
         if (SG[a] > 0) {
-            const C fm2 = static_cast<C>(fi[-2 * s]);
-            d = nnd_diff<1, C>(fm2, fm1, f0, fp1, C(0));
-            conv += vm * d;
-        } else {
-            const C fp2 = static_cast<C>(fi[2 * s]);
-            d = nnd_diff<-1, C>(C(0), fm1, f0, fp1, fp2);
-            conv -= vm * d;
+            const C fm2 = static_cast<C>(fi[-2 * s]), fm1 = static_cast<C>(fi[-s]), fp1 = static_cast<C>(fi[s]);
+            const C e0 = f0 - fm1, e1 = fp1 - f0;
+            D[a] = nnd_pos(fm1 - fm2, e0, e1);
+            L[a] = e1 - e0;
+        } else if (SG[a] < 0) {
+            const C fm1 = static_cast<C>(fi[-s]), fp1 = static_cast<C>(fi[s]), fp2 = static_cast<C>(fi[2 * s]);
+            const C e0 = f0 - fm1, e1 = fp1 - f0;
+            D[a] = nnd_neg(e0, e1, fp2 - fp1);
+            L[a] = e1 - e0;
+        } else if (G <= 1) {
+            L[a] = static_cast<C>(fi[-s]) + static_cast<C>(fi[s]);
         }
     }
-    C out = f0 - m.k_adv * conv - m.k_bgk * (f0 - feq);
-    if constexpr (G <= 1) {
-        const C lap = ((static_cast<C>(fi[-1]) + static_cast<C>(fi[1])) +
-                       (static_cast<C>(fi[-sy]) + static_cast<C>(fi[sy]))) +
-                      (static_cast<C>(fi[-sz]) + static_cast<C>(fi[sz])) - C(6) * f0;
-        out += (G == 0 ? m.k_lap0 : m.k_lap1) * lap;
-    }
-    *fo = static_cast<S>(out);
+    *fo = static_cast<S>(node_update<I, C>(f0, feq, D[0], D[1], D[2], L[0], L[1], L[2], m));
 }
 
 template <typename S, typename C, int I = 0>
@@ -103,12 +98,19 @@ template <int MODE, int BY>
 __global__ void __launch_bounds__(TILE_X * BY) LBM3D_TILED_ATTR
 k_step_tiled(StepArgs<MODE> A, Model<double> md, Model<float> mf, int ntx, int nty, int tz)
 {
-    __shared__ TilePlane<BY, typename Types<MODE>::S> P;
+    __shared__ TilePlane<BY, typename Types<MODE>::S> P[2];
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+#if LBM3D_TILE_ORDER_X
+    const int txi = t % ntx;
+    const int r = t / ntx;
+    const int tyi = r % nty;
+    const int tzi = r / nty;
+#else
     const int tyi = t % nty;
     const int r = t / nty;
     const int txi = r % ntx;
     const int tzi = r / ntx;
+#endif
     const int z0 = tzi * tz;
     const int z1 = min(z0 + tz, A.g.nz);
     step_tile<MODE, BY>(A, md, mf, txi * TILE_X, tyi * BY, z0, z1, P);
@@ -123,20 +125,21 @@ __global__ void __launch_bounds__(TILE_X * BY) LBM3D_TILED_ATTR
 k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict__ tiles, int ntiles, int parity)
 {
     using S = typename Types<MODE>::S;
-    __shared__ TilePlane<BY, S> P;
+    __shared__ TilePlane<BY, S> P[2];
     for (int t = (int)blockIdx.x; t < ntiles; t += (int)gridDim.x) {
         const BatchTile tile = tiles[t];
         const BatchSolve& d = solves[tile.solve];
         StepArgs<MODE> A;
         A.g = d.g;
         A.bc = d.bc;
-        A.fused = d.fused;
         const int cur = d.cur0 ^ parity;
         A.f = (const S*)d.f[cur];
         A.fn = (S*)d.f[cur ^ 1];
         A.health = d.health;
+#pragma unroll
+        for (int k = 0; k < 10; k++) A.xin[k / 5][k % 5] = d.xin[k / 5][k % 5];
         step_tile<MODE, BY>(A, d.md, d.mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
-        lds_barrier();  // the plane buffer is reused by the next tile
+        lds_barrier();  // the plane buffers are reused by the next tile
     }
 }
 
@@ -219,7 +222,7 @@ k_layers(StepArgs<MODE> A, Model<double> md, Model<float> mf, FixedStates fx, ui
             store_node(A.fn, g.sv, line + (uint32_t)(side ? n : -1) * st, e);
             store_node(A.fn, g.sv, line + (uint32_t)(side ? n + 1 : -2) * st, e);
         } else {
-            layer_line<MODE>(A, pick<M>(md, mf), pick<C>(md, mf), face, line, st, n, 0, n);
+            layer_line<MODE>(A, pick<M>(md, mf), pick<C>(md, mf), face, line, st, n);
         }
         return;
     }
@@ -365,55 +368,67 @@ hipError_t launch_init(int mode, const Grid& g, const Model<double>& md, const d
     return hipGetLastError();
 }
 
+bool tiled_fits(int mode, const Grid& g)
+{
+    // the tiled kernels address a velocity plane with 32-bit byte offsets
+    const int64_t es = mode == MODE_FP64 ? 8 : 4;
+    return g.sv * es < ((int64_t)1 << 31);
+}
+
 TileCfg default_tile(int mode, const Grid& g)
 {
     // measured on MI355X at 256x128x128: 64x8x32 tiles (FP32 modes) and
     // 64x4x64 (FP64); a short z extent leaves too few workgroups on small grids
     TileCfg t;
+    if (!tiled_fits(mode, g)) {
+        t.by = 0;
+        t.tz = 1;
+        return t;
+    }
     t.by = mode == MODE_FP64 ? 4 : 8;
     t.tz = mode == MODE_FP64 ? 64 : 32;
     if (g.nz < 2 * t.tz) t.tz = std::max(2, g.nz / 4);
     return t;
 }
 
-bool tile_supported(int mode, const TileCfg& t)
+bool tile_supported(int mode, const Grid& g, const TileCfg& t)
 {
     if (t.tz < 1) return false;
     if (t.by == 0) return true;
+    if (!tiled_fits(mode, g)) return false;
     if (t.by == 2 || t.by == 4) return true;
     return t.by == 8 && mode != MODE_FP64;
 }
 
-uint32_t fused_faces(const Grid& g, const FaceBC& bc, const TileCfg& tc)
+uint32_t ghost_faces(const Grid& g, const FaceBC& bc, bool tiled)
 {
-    if (tc.by == 0 || !LBM3D_FUSE_LAYERS) return 0u;  // layers left to the boundary-layer kernel
     uint32_t m = 0;
-    const int n[3] = {g.nx, g.ny, g.nz};
-    const int ext[3] = {TILE_X, tc.by, tc.tz};  // tile extent per axis
     for (int face = 0; face < 6; face++) {
-        const int k = bc.kind[face], a = face >> 1;
-        if (k == BC_PERIODIC || k == BC_REFLECT) m |= 1u << face;
-        // extrapolation reads the two nodes next to the face: both must lie
-        // in one tile (tiles start at multiples of the extent from 0)
-        if (k == BC_OUTFLOW && ext[a] >= 2) {
-            const bool ok = (face & 1) ? ((n[a] - 1) % ext[a]) != 0 : true;
-            if (ok) m |= 1u << face;
-        }
+        const int kind = bc.kind[face], axis = face >> 1;
+        if (kind == BC_INFLOW) continue;
+        if (tiled && LBM3D_X_IN_TILE && axis == 0 && g.nx % TILE_X == 0) continue;
+        if (tiled && LBM3D_WRAP_YZ && axis > 0 && kind == BC_PERIODIC) continue;
+        m |= 1u << face;
     }
     return m;
 }
 
-uint32_t ghost_faces(const FaceBC& bc, uint32_t fused)
+void x_fixed_states(const double (*inflow)[5], double (&xin)[2][5])
 {
-    uint32_t m = 0;
-    for (int face = 0; face < 6; face++)
-        if (bc.kind[face] != BC_INFLOW && !((fused >> face) & 1)) m |= 1u << face;
-    return m;
+    for (int s = 0; s < 2; s++) {
+        const double* st = inflow[s];
+        xin[s][0] = st[0];
+        xin[s][1] = st[1];
+        xin[s][2] = st[2];
+        xin[s][3] = st[3];
+        xin[s][4] = st[0] > 0.0 ? st[4] / st[0] : 0.0;  // T = p / rho
+    }
 }
 
 template <int MODE, int BY>
-static void launch_tiled(const Grid& g, const FaceBC& bc, uint32_t fused, int tz, const Model<double>& md,
-                         const Model<float>& mf, const void* f, void* fn, uint32_t* health, hipStream_t s)
+static void launch_tiled(const Grid& g, const FaceBC& bc, int tz, const Model<double>& md,
+                         const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
+                         uint32_t* health, hipStream_t s)
 {
     using S = typename Types<MODE>::S;
     const int ntx = (g.nx + TILE_X - 1) / TILE_X;
@@ -423,27 +438,26 @@ static void launch_tiled(const Grid& g, const FaceBC& bc, uint32_t fused, int tz
     StepArgs<MODE> A;
     A.g = g;
     A.bc = bc;
-    A.fused = fused;
     A.f = (const S*)f;
     A.fn = (S*)fn;
     A.health = health;
+    x_fixed_states(inflow, A.xin);
     k_step_tiled<MODE, BY><<<dim3(nb), dim3(TILE_X * BY), 0, s>>>(A, md, mf, ntx, nty, tz);
 }
 
 hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg& tc, const Model<double>& md,
-                       const Model<float>& mf, const void* f, void* fn, uint32_t* health,
-                       hipStream_t s)
+                       const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
+                       uint32_t* health, hipStream_t s)
 {
     if (tc.by != 0) {
-        const uint32_t fu = fused_faces(g, bc, tc);
         switch (tc.by) {
-        case 2: LBM3D_DISPATCH(mode, launch_tiled<MD, 2>(g, bc, fu, tc.tz, md, mf, f, fn, health, s)); break;
+        case 2: LBM3D_DISPATCH(mode, launch_tiled<MD, 2>(g, bc, tc.tz, md, mf, inflow, f, fn, health, s)); break;
         case 8:
             if (mode == MODE_FP64) return hipErrorInvalidValue;
-            if (mode == MODE_FP32) launch_tiled<MODE_FP32, 8>(g, bc, fu, tc.tz, md, mf, f, fn, health, s);
-            else launch_tiled<MODE_FP32_T64, 8>(g, bc, fu, tc.tz, md, mf, f, fn, health, s);
+            if (mode == MODE_FP32) launch_tiled<MODE_FP32, 8>(g, bc, tc.tz, md, mf, inflow, f, fn, health, s);
+            else launch_tiled<MODE_FP32_T64, 8>(g, bc, tc.tz, md, mf, inflow, f, fn, health, s);
             break;
-        default: LBM3D_DISPATCH(mode, launch_tiled<MD, 4>(g, bc, fu, tc.tz, md, mf, f, fn, health, s)); break;
+        default: LBM3D_DISPATCH(mode, launch_tiled<MD, 4>(g, bc, tc.tz, md, mf, inflow, f, fn, health, s)); break;
         }
         return hipGetLastError();
     }
@@ -483,8 +497,7 @@ hipError_t launch_ghosts(int mode, const Grid& g, const FaceBC& bc, const Model<
         StepArgs<MD> A{};
         A.g = g;
         A.bc = bc;
-        A.fused = 0;
-        A.f = nullptr;
+            A.f = nullptr;
         A.fn = (typename Types<MD>::S*)f;
         A.health = nullptr;
         k_layers<MD><<<dim3(nb), dim3(64), 0, s>>>(A, md, mf, fx, faces);

@@ -27,6 +27,7 @@ struct Model {
     T k_adv;             // dt/dx
     T k_bgk;             // dt/tau
     T k_lap0, k_lap1;    // lambda_1 dt/dx^2 (rest), lambda_{2..7} dt/dx^2 (axis)
+    T a1, ad;            // dt/dx c1 and dt/dx c2/sqrt(3): advection factors per axis
 };
 
 // Geometry of one solve's padded distribution array f[15][mz][my][mx]:
@@ -58,8 +59,8 @@ struct BatchTile {
 struct BatchSolve {
     Grid g;
     FaceBC bc;
-    uint32_t fused;       // faces whose boundary layers the step writes itself
     int32_t cur0;         // buffer holding the current level at batch step 0
+    double xin[2][5];     // fixed states of the x faces (rho, ux, uy, uz, T)
     void* f[2];           // the two distribution buffers
     uint32_t* health;
     Model<double> md;
@@ -76,14 +77,21 @@ struct TileCfg {
     int tz = 16;
 };
 TileCfg default_tile(int mode, const Grid& g);
-bool tile_supported(int mode, const TileCfg& t);
-// faces whose boundary layers the step kernel writes itself, and the
-// non-fixed faces left to the boundary-layer kernel
-uint32_t fused_faces(const Grid& g, const FaceBC& bc, const TileCfg& tc);
-uint32_t ghost_faces(const FaceBC& bc, uint32_t fused);
+bool tile_supported(int mode, const Grid& g, const TileCfg& t);
+// the tiled kernels (single and batched) take this solve
+bool tiled_fits(int mode, const Grid& g);
+// Faces whose boundary layers the boundary-layer kernel refreshes after
+// every step.  Fixed-state layers are written once at init.  The tiled
+// kernels form the x layers themselves when 64-wide tiles cover x exactly
+// (nx a multiple of 64) and wrap periodic y and z faces, so with `tiled`
+// those faces need no layers in memory.
+uint32_t ghost_faces(const Grid& g, const FaceBC& bc, bool tiled);
 hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg& tc, const Model<double>& md,
-                       const Model<float>& mf, const void* f, void* fn, uint32_t* health,
-                       hipStream_t s);
+                       const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
+                       uint32_t* health, hipStream_t s);
+// (rho, ux, uy, uz, T) of the two x faces' fixed states, from the ABI's
+// (rho, ux, uy, uz, p)
+void x_fixed_states(const double (*inflow)[5], double (&xin)[2][5]);
 hipError_t launch_ghosts(int mode, const Grid& g, const FaceBC& bc, const Model<double>& md,
                          const double (*inflow)[5], bool include_fixed, void* f, hipStream_t s,
                          uint32_t face_mask = 0x3fu);

@@ -2,6 +2,8 @@
 // moment recovery, equilibrium, minmod and the per-node update.
 #pragma once
 
+#include <type_traits>
+
 #include "lbm3d_internal.h"
 
 namespace lbm3d {
@@ -64,45 +66,75 @@ __device__ __forceinline__ Macro<M> moments(const C (&f)[NV], const Model<M>& m)
     return q;
 }
 
-// f^eq = rho (A + B s + D s^2) of Eqs. (eq)/(e18) for all 15 velocities.
-// The group coefficients A, B depend on T and u^2 and are formed in the
-// moment type M; the 15 values are then evaluated in the bulk type C.
+// Group coefficients of Eqs. (eq)/(e18) for one macroscopic state: A and B
+// of each group depend on T and u^2 and are formed in the moment type M,
+// then everything is taken to the bulk type C.
+template <typename C>
+struct EqCoef {
+    C rho, ar, ax, bx, ad, bd, ux, uy, uz;
+};
+
+template <typename C, typename M>
+__device__ __forceinline__ EqCoef<C> eq_coef(const Macro<M>& q, const Model<M>& mm)
+{
+    const M usq = q.ux * q.ux + q.uy * q.uy + q.uz * q.uz;
+    EqCoef<C> c;
+    c.rho = static_cast<C>(q.rho);
+    c.ar = static_cast<C>(mm.r_aT * q.T);
+    c.ax = static_cast<C>(mm.x_a0 + mm.x_aT * q.T + mm.x_au * usq);
+    c.bx = static_cast<C>(mm.x_b0 + mm.x_bT * q.T + mm.x_bu * usq);
+    c.ad = static_cast<C>(mm.d_a0 + mm.d_aT * q.T + mm.d_au * usq);
+    c.bd = static_cast<C>(mm.d_b0 + mm.d_bT * q.T + mm.d_bu * usq);
+    c.ux = static_cast<C>(q.ux);
+    c.uy = static_cast<C>(q.uy);
+    c.uz = static_cast<C>(q.uz);
+    return c;
+}
+
+// f_i^eq = rho (A + B s + D s^2), s = v_i.u, for velocity i.  The same
+// operations for a compile-time i (folded) and a per-lane i (selected), so
+// both agree bitwise.  Each value is its own statement: with expression-
+// local contraction the rounding then does not depend on the caller.
+template <typename C>
+__device__ __forceinline__ C feq_vel(int i, const EqCoef<C> c, const Model<C>& mc)
+{
+    if (i == 0) return c.rho * c.ar;
+    if (i <= 6) {
+        // (selects on values: an index into the struct would send it to
+        // private memory)
+        const int a = (i - 1) >> 1;
+        const C ux = c.ux, uy = c.uy, uz = c.uz;
+        const C uyz = a == 1 ? uy : uz;
+        const C u = a == 0 ? ux : uyz;
+        const C s = mc.c1 * u;
+        const C t = mc.x_d * s;
+        const C w = t * s + c.ax;
+        const C even = c.rho * w;
+        const C bs = c.bx * s;
+        const C odd = c.rho * bs;
+        return ((i - 1) & 1) ? even - odd : even + odd;
+    }
+    // diagonal d = i - 7, signs (bit0: x, bit1: y, bit2: z); normalised so
+    // that the x sign is +, s is +/- k ((ux +/- uy) +/- uz)
+    const int d = i - 7;
+    const bool fy = ((d >> 1) ^ d) & 1, fz = ((d >> 2) ^ d) & 1;  // y, z sign differs from x
+    const C b = fy ? c.ux - c.uy : c.ux + c.uy;
+    const C t = fz ? b - c.uz : b + c.uz;
+    const C sv = mc.k * t;
+    const C s = (d & 1) ? -sv : sv;
+    const C h = mc.d_d * s + c.bd;
+    const C w = s * h + c.ad;
+    return c.rho * w;
+}
+
+// f^eq of Eqs. (eq)/(e18) for all 15 velocities.
 template <typename C, typename M>
 __device__ __forceinline__ void equilibrium(const Macro<M>& q, const Model<M>& mm,
                                             const Model<C>& mc, C (&feq)[NV])
 {
-    const M usq = q.ux * q.ux + q.uy * q.uy + q.uz * q.uz;
-    const C rho = static_cast<C>(q.rho);
-    const C ar = static_cast<C>(mm.r_aT * q.T);
-    const C ax = static_cast<C>(mm.x_a0 + mm.x_aT * q.T + mm.x_au * usq);
-    const C bx = static_cast<C>(mm.x_b0 + mm.x_bT * q.T + mm.x_bu * usq);
-    const C ad = static_cast<C>(mm.d_a0 + mm.d_aT * q.T + mm.d_au * usq);
-    const C bd = static_cast<C>(mm.d_b0 + mm.d_bT * q.T + mm.d_bu * usq);
-    const C ux = static_cast<C>(q.ux), uy = static_cast<C>(q.uy), uz = static_cast<C>(q.uz);
-    feq[0] = rho * ar;
-    const C u3[3] = {ux, uy, uz};
+    const EqCoef<C> c = eq_coef<C, M>(q, mm);
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const C s = mc.c1 * u3[a];
-        const C even = rho * (ax + mc.x_d * s * s);
-        const C odd = rho * (bx * s);
-        feq[1 + 2 * a] = even + odd;
-        feq[2 + 2 * a] = even - odd;
-    }
-    // four |s| classes of the diagonal group: s and -s share A + D s^2
-    const C sxy = ux + uy, dxy = ux - uy;
-    const C sv[4] = {mc.k * (sxy + uz), mc.k * (dxy + uz), mc.k * (sxy - uz), mc.k * (dxy - uz)};
-    // diagonal d has signs (bit0: x, bit1: y, bit2: z); its s equals
-    // +sv[c] or -sv[c] for the class c below
-#pragma unroll
-    for (int d = 0; d < 8; d++) {
-        const int sx = (d & 1) ? -1 : 1, sy = (d & 2) ? -1 : 1, sz = (d & 4) ? -1 : 1;
-        // normalise so the x sign is +: classes (+,+,+), (+,-,+), (+,+,-), (+,-,-)
-        const int ny = sy * sx, nz = sz * sx;
-        const int c = (ny < 0 ? 1 : 0) + (nz < 0 ? 2 : 0);
-        const C s = sx > 0 ? sv[c] : -sv[c];
-        feq[7 + d] = rho * (ad + s * (bd + mc.d_d * s));
-    }
+    for (int i = 0; i < NV; i++) feq[i] = feq_vel<C>(i, c, mc);
 }
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_INFLOW = 2, BC_REFLECT = 3 };
@@ -129,33 +161,92 @@ __device__ __forceinline__ uint32_t health_bits(const Macro<M>& q)
     return h;
 }
 
-// ---------------------------------------------------- NND flux, one axis --
-// Face values of the NND reconstruction along one axis for a velocity
-// component of sign SG (Sec. 3, Eq. (nnd)): with h = v g,
-//   v > 0:  g_{I+1/2} = f_I + mm(f_{I+1}-f_I, f_I-f_{I-1}) / 2
-//   v < 0:  g_{I+1/2} = f_{I+1} - mm(f_{I+1}-f_I, f_{I+2}-f_{I+1}) / 2
-// (the f^+ / f^- split with minmod odd and positively homogeneous).
-// Returns g_{I+1/2} - g_{I-1/2}; fm2..fp2 are f at I-2..I+2 (the two values
-// on the downwind far side are not used).
-// Face value g_{I+1/2} for v > 0 from f_{I-1}, f_I, f_{I+1}.
+// ------------------------------------------------------- per-node update --
+// Explicit fused multiply-add, so that every kernel rounds the update the
+// same way whatever the compiler's contraction choices in its context.
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// NND flux difference along one axis (Sec. 3, Eq. (nnd)).  With h = v g and
+// e_k = f_{I+k} - f_{I+k-1} the differences of consecutive nodes:
+//   v > 0:  g_{I+1/2} = f_I + mm(e_1, e_0)/2, so
+//           g_{I+1/2} - g_{I-1/2} = e_0 + (mm(e_1, e_0) - mm(e_0, e_-1)) / 2;
+//   v < 0:  g_{I+1/2} = f_{I+1} - mm(e_1, e_2)/2, so
+//           g_{I+1/2} - g_{I-1/2} = e_1 - (mm(e_1, e_2) - mm(e_0, e_1)) / 2
+// (the f^+ / f^- split of the paper, minmod being odd and positively
+// homogeneous).  The _c forms take the second minmod from the node before
+// along the axis and return the first one for the node after: a sweep along
+// the axis then evaluates one minmod per node, with bitwise the same result.
 template <typename C>
-__device__ __forceinline__ C face_pos(C fm1, C f0, C fp1)
+__device__ __forceinline__ C nnd_pos(C em1, C e0, C e1)
 {
-    return f0 + C(0.5) * minmod(fp1 - f0, f0 - fm1);
+    return fmac(C(0.5), minmod(e1, e0) - minmod(e0, em1), e0);
 }
-// Face value g_{I+1/2} for v < 0 from f_I, f_{I+1}, f_{I+2}.
 template <typename C>
-__device__ __forceinline__ C face_neg(C f0, C fp1, C fp2)
+__device__ __forceinline__ C nnd_neg(C e0, C e1, C e2)
 {
-    return fp1 - C(0.5) * minmod(fp1 - f0, fp2 - fp1);
+    return fmac(C(-0.5), minmod(e1, e2) - minmod(e0, e1), e1);
 }
-template <int SG, typename C>
-__device__ __forceinline__ C nnd_diff(C fm2, C fm1, C f0, C fp1, C fp2)
+template <typename C>
+__device__ __forceinline__ C nnd_pos_c(C e0, C e1, C& mprev)
 {
-    if constexpr (SG > 0)
-        return face_pos(fm1, f0, fp1) - face_pos(fm2, fm1, f0);
-    else
-        return face_neg(f0, fp1, fp2) - face_neg(fm1, f0, fp1);
+    const C m = minmod(e1, e0);
+    const C d = fmac(C(0.5), m - mprev, e0);
+    mprev = m;
+    return d;
+}
+template <typename C>
+__device__ __forceinline__ C nnd_neg_c(C e1, C e2, C& mprev)
+{
+    const C m = minmod(e1, e2);
+    const C d = fmac(C(-0.5), m - mprev, e1);
+    mprev = m;
+    return d;
+}
+
+// Laplacian of Eq. (lp) from one part per axis: along an axis the velocity
+// is advected on, the part is e_1 - e_0 = f_{I+1} - 2 f_I + f_{I-1}; along
+// the other axes it is f_{I+1} + f_{I-1}, whose -2 f_I terms are added once.
+template <int I, typename C>
+__device__ __forceinline__ C lap_sum(C lx, C ly, C lz, C f0)
+{
+    constexpr int G = vgroup(I);
+    if constexpr (G == 0) {
+        return fmac(C(-6), f0, (lx + ly) + lz);
+    } else {
+        constexpr int ax = (I - 1) >> 1;
+        const C own = ax == 0 ? lx : (ax == 1 ? ly : lz);
+        const C pb = ax == 0 ? ly : lx;
+        const C pc = ax == 2 ? ly : lz;
+        return own + fmac(C(-4), f0, pb + pc);
+    }
+}
+
+// f_i^{n+1} of Eq. (fi1) for velocity I from its flux differences along x,
+// y, z (those with v_ia = 0 are ignored) and Laplacian parts (used for the
+// rest and axis velocities):
+//   f + dt/tau (f^eq - f) - dt/dx sum_a v_ia D_a + lambda_i dt/dx^2 Lap f.
+template <int I, typename C>
+__device__ __forceinline__ C node_update(C f0, C feq, C dx_, C dy_, C dz_, C lx, C ly, C lz, const Model<C>& m)
+{
+    constexpr int SX = vsign(I, 0), SY = vsign(I, 1), SZ = vsign(I, 2), G = vgroup(I);
+    const C a = (G == 1) ? m.a1 : m.ad;  // dt/dx |v_ia|
+    C acc = fmac(m.k_bgk, feq - f0, f0);
+    if constexpr (SX != 0) acc = fmac(SX > 0 ? -a : a, dx_, acc);
+    if constexpr (SY != 0) acc = fmac(SY > 0 ? -a : a, dy_, acc);
+    if constexpr (SZ != 0) acc = fmac(SZ > 0 ? -a : a, dz_, acc);
+    if constexpr (G <= 1) acc = fmac(G == 0 ? m.k_lap0 : m.k_lap1, lap_sum<I, C>(lx, ly, lz, f0), acc);
+    return acc;
+}
+
+// Compile-time loop.
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
 }
 
 }  // namespace lbm3d

@@ -238,6 +238,7 @@ int32_t lbm3d_server_submit(lbm3d_server_t s, const lbm3d_params* p, const doubl
     int32_t rc = lbm3d_footprint(p, &fp);
     if (rc) return rc;
     if (fp > s->budget) return LBM3D_E_NOMEM;
+    if (!lbm3d::tiled_fits(p->precision, lbm3d::make_grid(p))) return LBM3D_E_INVAL;  // batched kernel's limit
     const size_t n = (size_t)p->nx * p->ny * p->nz;
     for (size_t k = 0; k < n; k++)
         if (!(rho[k] > 0.0) || !(pr[k] > 0.0)) return LBM3D_E_INVAL;

@@ -1,45 +1,50 @@
-// The fused FD-LB time step on one tile of 64 x BY nodes marching along z.
+// The fused FD-LB time step on one tile of 64 x BY nodes marching along z,
+// and the boundary-layer rules of Sec. 4 (2).
 //
 // Data flow per tile (a workgroup of BY wavefronts, one x-row of 64 nodes
 // per wavefront):
-//   - every thread keeps, per velocity, a short queue of its column's values
-//     along z (f at z-1 .. z+2 as the upwind side needs) in registers, plus
-//     the NND face value g_{z-1/2} of the previous z step, so the z
-//     direction costs one new face per velocity and step and one global
-//     load per velocity (the plane two or three ahead, prefetched);
+//   - along z every thread keeps, per velocity, a ring of four of its
+//     column's values (z-1 .. z+2, or z .. z+3 for v_z < 0) and the minmod
+//     of the previous z face, so z costs one global load, one new difference
+//     and one minmod per velocity and plane; the z loop is unrolled over the
+//     ring's four phases so that no value is ever moved, and each plane's
+//     load goes straight into the ring slot it will be read from a plane
+//     later;
 //   - the current z plane of all 15 velocities is staged in LDS with the
-//     face halo the x and y stencils need (two nodes on the upwind side, one
-//     on the other; one on each side for the dissipation of the rest and
-//     axis velocities).  Halo rows are read by whole wavefronts (64
-//     consecutive x); the halo columns of a row are gathered into one
-//     register per wavefront.  The halo of the next plane is loaded while
-//     the current one is computed, so the LDS barriers are the only waits on
-//     the critical path;
+//     halo the x and y stencils need (two nodes on the upwind side, one on
+//     the other; one on each side for the dissipation of the rest and axis
+//     velocities).  Two LDS planes alternate, so one barrier per plane
+//     separates staging from reading.  Halo rows are read by whole
+//     wavefronts (64 consecutive x) through a uniform job table; the halo
+//     columns of a row are gathered into one register per wavefront; a
+//     plane's halo is loaded two planes ahead, with the ring loads of the
+//     same plane;
+//   - global memory is addressed as a uniform (scalar) base per velocity
+//     and plane plus one 32-bit per-lane byte offset;
 //   - moments, equilibrium, NND convection in x, y, z, dissipation and the
 //     BGK forward-Euler update are evaluated in registers and each new f is
-//     written once;
-//   - the boundary layers of the new level are written by a separate,
-//     light launch (one thread per boundary line); a build option moves
-//     the periodic and reflecting ones into the tiles next to the face.
-// Per node, the arithmetic is the same sequence of operations as a direct
-// evaluation of the stencil, so results do not depend on the tile shape.
+//     written once.
+// Per node the arithmetic is node_update() and the NND helpers, shared with
+// the one-node-per-thread kernel, so results do not depend on the launch
+// shape.
 #pragma once
 
 #include "lbm3d_model.h"
 
 namespace lbm3d {
 
-// Build-time tuning knobs of the sweep (defaults are the tuned choice):
-// LBM3D_HALO_PREFETCH loads the next plane's halo during the current
-// plane's compute (1) or right before staging it (0).
-#ifndef LBM3D_HALO_PREFETCH
-#define LBM3D_HALO_PREFETCH 1
+// Build-time tuning knobs: tiles are numbered with x fastest (1) or y
+// fastest (0) before the XCD grouping; the tiles form the x boundary layers
+// themselves (1) or read them from memory (0); periodic y / z faces wrap
+// (1) or are read from memory (0).
+#ifndef LBM3D_TILE_ORDER_X
+#define LBM3D_TILE_ORDER_X 1
 #endif
-// LBM3D_FUSE_LAYERS: 1 = the tiled step writes the boundary layers whose
-// source nodes a tile owns (after its sweep); 0 = a separate launch of the
-// boundary-layer kernel writes all of them.
-#ifndef LBM3D_FUSE_LAYERS
-#define LBM3D_FUSE_LAYERS 0
+#ifndef LBM3D_X_IN_TILE
+#define LBM3D_X_IN_TILE 1
+#endif
+#ifndef LBM3D_WRAP_YZ
+#define LBM3D_WRAP_YZ 1
 #endif
 
 // Workgroup barrier that orders LDS accesses only: global loads in flight
@@ -99,10 +104,10 @@ struct StepArgs {
     using S = typename Types<MODE>::S;
     Grid g;
     FaceBC bc;
-    uint32_t fused;  // faces whose boundary layers the step kernel writes itself
     const S* f;
     S* fn;
     uint32_t* health;
+    double xin[2][5];  // fixed states of the x faces (rho, ux, uy, uz, T)
 };
 
 // Extrapolated boundary states of Sec. 4 (2): layer 1 = 2 q(i0) - q(i1),
@@ -148,29 +153,14 @@ __device__ __forceinline__ void store_node(S* __restrict__ fn, int64_t sv, uint3
     for (int i = 0; i < NV; i++) (fn + i * sv)[off] = static_cast<S>(v[i]);
 }
 
-// Does a tile owning nodes [lo, hi) along an axis of n nodes write layer
-// nodes of this face?  Periodic: a layer node copies node (slot mod n), and
-// the owner of that node writes it.  Reflecting / extrapolating: the owner
-// of the node next to the face (the host fuses an extrapolating face only if
-// the second node in lies in the same tile).
-__device__ __forceinline__ bool layer_owner(int kind, int side, int n, int lo, int hi)
-{
-    if (kind == BC_INFLOW) return false;
-    if (kind == BC_PERIODIC) {
-        const int s1 = side ? (n % n) : (((-1 % n) + n) % n);
-        const int s2 = side ? ((n + 1) % n) : (((-2 % n) + n) % n);
-        return (s1 >= lo && s1 < hi) || (s2 >= lo && s2 < hi);
-    }
-    const int i0 = side ? n - 1 : 0;
-    return i0 >= lo && i0 < hi;
-}
-
-// Layer nodes of one face on the line through `line` (offset of the line's
-// node 0 along the axis, node stride st), for a tile owning [lo, hi).
+// Boundary layers of one face on the line of nodes through `line` (offset
+// of the line's node 0, node stride st along the face normal, n nodes):
+// periodic copy, reflecting wall or linear extrapolation, the layer f being
+// the equilibrium of the layer state.
 template <int MODE>
 __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<typename Types<MODE>::M>& mm,
                                            const Model<typename Types<MODE>::C>& mc, int face, uint32_t line,
-                                           uint32_t st, int n, int lo, int hi)
+                                           uint32_t st, int n)
 {
     using S = typename Types<MODE>::S;
     using C = typename Types<MODE>::C;
@@ -186,7 +176,6 @@ __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<
 #pragma unroll
         for (int k = 0; k < 2; k++) {
             const int src = ((gs[k] % n) + n) % n;
-            if (src < lo || src >= hi) continue;
 #pragma unroll
             for (int i = 0; i < NV; i++) a[i] = static_cast<C>((fn + i * sv)[at(src)]);
             store_node(fn, sv, at(gs[k]), a);
@@ -212,14 +201,110 @@ __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<
     store_node(fn, sv, at(g2), a);
 }
 
-template <int MODE, int BY>
-__device__ __forceinline__ void step_tile(const StepArgs<MODE>& A, const Model<double>& md,
-                                          const Model<float>& mf, int x0, int y0, int z0, int z1,
-                                          TilePlane<BY, typename Types<MODE>::S>& P)
+// Ring slot of plane z + j of velocity I's column at unroll phase K: the
+// ring holds planes z-1 .. z+2 (v_z >= 0) or z .. z+3 (v_z < 0).
+template <int I>
+__host__ __device__ constexpr int ring_slot(int j, int K)
+{
+    return vsign(I, 2) < 0 ? ((K + j) & 3) : ((K + j + 1) & 3);
+}
+
+// A uniform pointer made opaque to the optimiser: it stays in scalar
+// registers and per-lane offsets are not re-associated into it, so each
+// access is one scalar base plus one 32-bit lane offset (the base of the
+// next velocity plane is one scalar add away).
+template <typename T>
+__device__ __forceinline__ T* sreg(T* p)
+{
+    uint64_t v = reinterpret_cast<uint64_t>(p);
+    asm("" : "+s"(v));
+    return reinterpret_cast<T*>(v);
+}
+
+// Global access through a uniform base pointer and a 32-bit byte offset
+// (global address space, so the scalar-base form of the instruction applies).
+// The offset is passed through an empty asm so that its zero extension is
+// formed at the access (and matched there) rather than hoisted as a 64-bit
+// value.
+template <typename S>
+__device__ __forceinline__ S ld_at(const S* base, uint32_t off)
+{
+    using GP = const __attribute__((address_space(1))) S*;
+    asm("" : "+v"(off));
+    return *reinterpret_cast<GP>(reinterpret_cast<uint64_t>(base) + (uint64_t)off);
+}
+// Stores of the new level are streaming (non-temporal): they are not read
+// again in this step, and keeping them out of the L2 leaves it to the
+// planes that neighbouring tiles read as their halos.
+#ifndef LBM3D_NT_STORE
+#define LBM3D_NT_STORE 1
+#endif
+template <typename S>
+__device__ __forceinline__ void st_at(S* base, uint32_t off, S v)
+{
+    using GP = __attribute__((address_space(1))) S*;
+    asm("" : "+v"(off));
+    GP p = reinterpret_cast<GP>(reinterpret_cast<uint64_t>(base) + (uint64_t)off);
+#if LBM3D_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+// Index v in [-2, n + 9] wrapped into [0, n) (periodic faces).
+__device__ __forceinline__ int wrap_idx(int v, int n)
+{
+    if (n >= 10) return v < 0 ? v + n : (v >= n ? v - n : v);
+    return ((v % n) + n) % n;
+}
+
+// Value held by lane l (per lane) of this wavefront.
+__device__ __forceinline__ float lane_get(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(l << 2, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_get(double v, int l)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <typename M>
+__device__ __forceinline__ Macro<M> shfl_macro(const Macro<M>& q, int l)
+{
+    Macro<M> r;
+    r.rho = lane_get(q.rho, l);
+    r.ux = lane_get(q.ux, l);
+    r.uy = lane_get(q.uy, l);
+    r.uz = lane_get(q.uz, l);
+    r.T = lane_get(q.T, l);
+    return r;
+}
+template <typename M>
+__device__ __forceinline__ Macro<M> pick_macro(bool b, const Macro<M>& x, const Macro<M>& y)
+{
+    Macro<M> r;
+    r.rho = b ? x.rho : y.rho;
+    r.ux = b ? x.ux : y.ux;
+    r.uy = b ? x.uy : y.uy;
+    r.uz = b ? x.uz : y.uz;
+    r.T = b ? x.T : y.T;
+    return r;
+}
+
+// XF: this tile forms extrapolating or reflecting x layers itself (see
+// x_forms(); the caller selects the instantiation per tile).
+template <int MODE, int BY, bool XF>
+__device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model<double>& md,
+                                            const Model<float>& mf, int x0, int y0, int z0, int z1,
+                                            TilePlane<BY, typename Types<MODE>::S> (&P)[2])
 {
     using S = typename Types<MODE>::S;
     using C = typename Types<MODE>::C;
     using M = typename Types<MODE>::M;
+    constexpr uint32_t ES = sizeof(S);
     const Model<C>& mc = pick<C>(md, mf);
     const Model<M>& mm = pick<M>(md, mf);
     const Grid& g = A.g;
@@ -231,225 +316,307 @@ __device__ __forceinline__ void step_tile(const StepArgs<MODE>& A, const Model<d
     const int wave = __builtin_amdgcn_readfirstlane(ty);
     const int x = x0 + tx, y = y0 + ty;
     const bool act = (x < g.nx) && (y < g.ny);
-    // every load is clamped into the padded array: nodes beyond the last
-    // boundary layer are never read by an active node's stencil.  Velocity
-    // planes are addressed as a uniform base pointer plus one 32-bit
-    // per-thread offset (a velocity plane holds < 2^31 elements).
-    const int xl = min(x, g.nx + 1), yl = min(y, g.ny + 1);
-    const int64_t sv = g.sv;
-    const uint32_t sy = (uint32_t)g.sy, sz = (uint32_t)g.sz;
-    const uint32_t col = (uint32_t)(g.org + (int64_t)yl * g.sy + xl);
-    const uint32_t rowoff = (uint32_t)(g.org + xl);
+    const int64_t sv = g.sv, sy = g.sy, sz = g.sz;
+    const int zmax = g.nz + 1;
+    // Faces handled inside the tile, so their layers need not be in memory:
+    //  - x faces when 64-wide tiles cover x exactly: periodic halo columns
+    //    wrap; fixed-state columns are written into both LDS planes once;
+    //    extrapolated and reflecting columns are formed per plane from the
+    //    moments of the nodes next to the face (Sec. 4 (2)), by the
+    //    wavefront that owns the row;
+    //  - periodic y and z faces: rows and planes wrap.
+    // Other layers are read from memory.  Every load is clamped into the
+    // padded array: nodes beyond the last layer are never read by an
+    // active node's stencil.
+    const bool xin_tile = LBM3D_X_IN_TILE && (g.nx % TILE_X) == 0;
+    const bool lf = xin_tile && x0 == 0, rf = xin_tile && x0 + TILE_X == g.nx;
+    const int kL = A.bc.kind[0], kR = A.bc.kind[1];
+    const bool ywrap = LBM3D_WRAP_YZ && A.bc.kind[2] == BC_PERIODIC;
+    const bool zwrap = LBM3D_WRAP_YZ && A.bc.kind[4] == BC_PERIODIC;
+    auto zsel = [&](int zz) { return zwrap ? wrap_idx(zz, g.nz) : min(zz, zmax); };
+    const int xl = min(x, g.nx + 1);
+    const int yl = ywrap ? wrap_idx(min(y, g.ny + 9), g.ny) : min(y, g.ny + 1);
+    // uniform base of velocity i at plane zz (node (0, 0, zz))
+    auto base = [&](const S* p, int i, int zz) { return p + ((int64_t)i * sv + g.org + (int64_t)zz * sz); };
+    auto wbase = [&](S* p, int i, int zz) { return p + ((int64_t)i * sv + g.org + (int64_t)zz * sz); };
+    const uint32_t colb = (uint32_t)((int64_t)yl * sy + xl) * ES;  // this thread's node within a plane
+    const uint32_t xlb = (uint32_t)xl * ES;
+    // lanes outside the grid store to a sink element past the end of each
+    // velocity plane that is never read, so every store is unconditional
+    const int64_t sinkrel = g.sink - g.org;
 
-    C q[NV][4];  // f at z-1, z, z+1, z+2 along this thread's column
-    C gp[NV];    // NND face value g_{z-1/2} of the z-advected velocities
-#pragma unroll
-    for (int i = 0; i < NV; i++) {
-        const S* fi = f + i * sv;
-        q[i][0] = static_cast<C>(fi[col + (uint32_t)(z0 - 1) * sz]);
-        q[i][1] = static_cast<C>(fi[col + (uint32_t)z0 * sz]);
-        q[i][2] = static_cast<C>(fi[col + (uint32_t)(z0 + 1) * sz]);
-        q[i][3] = C(0);
-        gp[i] = C(0);
-        if (vsign(i, 2) < 0) {
-            q[i][3] = static_cast<C>(fi[col + (uint32_t)(z0 + 2) * sz]);
-            gp[i] = face_neg(q[i][0], q[i][1], q[i][2]);
-        } else if (vsign(i, 2) > 0) {
-            const C fm2 = static_cast<C>(fi[col + (uint32_t)(z0 - 2) * sz]);
-            gp[i] = face_pos(fm2, q[i][0], q[i][1]);
+    // ---- z ring and carried minmods
+    C q[NV][4];
+    C mz[NV];
+    C ez6 = C(0);  // f_z - f_{z-1} of the -z axis velocity (its dissipation)
+    static_for<NV>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        constexpr int SZ = vsign(I, 2);
+        auto at = [&](int zz) { return static_cast<C>(ld_at(base(f, I, zz), colb)); };
+        q[I][3] = C(0);
+        mz[I] = C(0);
+        if constexpr (SZ < 0) {
+            q[I][0] = at(z0);
+            q[I][1] = at(zsel(z0 + 1));
+            q[I][2] = at(zsel(z0 + 2));
+            const C e0 = q[I][0] - at(zsel(z0 - 1));
+            mz[I] = minmod(e0, q[I][1] - q[I][0]);
+            if constexpr (I == 6) ez6 = e0;
+        } else {
+            q[I][0] = at(zsel(z0 - 1));
+            q[I][1] = at(z0);
+            q[I][2] = at(zsel(z0 + 1));
+            if constexpr (SZ > 0) mz[I] = minmod(q[I][1] - q[I][0], q[I][0] - at(zsel(z0 - 2)));
         }
-    }
+    });
 
-    // x halo of this wavefront's row, gathered into one register: lane
-    // 4v + p holds velocity v at x0-2, x0-1, x0+64, x0+65 for p = 0..3
+    // ---- halo of a plane: x columns gathered into one register (lane 4v+p
+    // holds velocity v at x0-2, x0-1, x0+64, x0+65 for p = 0..3) and the
+    // halo rows of this wavefront's jobs wave, wave + BY, ...
     const int hv = min(tx >> 2, NV - 1), hp = tx & 3;
-    const int hx = min(hp == 0 ? x0 - 2 : hp == 1 ? x0 - 1 : hp == 2 ? x0 + TILE_X : x0 + TILE_X + 1, g.nx + 1);
-    const S* hptr = f + hv * sv + (g.org + (int64_t)yl * g.sy + hx);
+    int hx = hp == 0 ? x0 - 2 : hp == 1 ? x0 - 1 : hp == 2 ? x0 + TILE_X : x0 + TILE_X + 1;
+    bool hlane = tx < 4 * NV;  // this lane's gathered value is staged
+    if (lf && hp < 2) {
+        if (kL == BC_PERIODIC) hx += g.nx;
+        else { hx = 0; hlane = false; }  // formed in the tile; load a cached column
+    }
+    if (rf && hp >= 2) {
+        if (kR == BC_PERIODIC) hx -= g.nx;
+        else { hx = g.nx - 1; hlane = false; }
+    }
+    hx = min(hx, g.nx + 1);
+    const S* hptr = f + ((int64_t)hv * sv + g.org + (int64_t)yl * sy + hx);
     const int hcol = hp < 2 ? hp : hp + TILE_X;
-    const bool hlane = tx < 4 * NV;
-    // halo rows of this wavefront: jobs wave, wave + BY, ...
     constexpr int NJ = halo_jobs();
     static_assert(NJ % BY == 0, "every wavefront stages the same number of halo rows");
     constexpr int NK = NJ / BY;
-    S hrow[NK];
-    S hcolv = S(0);
+    int yhk[NK];  // rows of this wavefront's halo jobs (uniform)
 #pragma unroll
-    for (int k = 0; k < NK; k++) hrow[k] = S(0);
-    auto load_halo = [&](int zz) {
-        const uint32_t zo = (uint32_t)zz * sz;
-        hcolv = hptr[zo];
+    for (int k = 0; k < NK; k++) {
+        const int e = kHaloJobs.e[wave + k * BY];
+        const int code = e & 3;
+        const int r = code < 2 ? code - 2 : BY + code - 2;
+        yhk[k] = ywrap ? wrap_idx(y0 + r, g.ny) : min(y0 + r, g.ny + 1);
+    }
+    // two register sets of halo values: the set of plane z+2 is loaded
+    // while the set of plane z+1 waits to be staged, so a tile reads its
+    // halo rows at the same time as the neighbouring tiles load them as
+    // their own planes (the L2 then serves one of the two)
+    S hrow[2][NK];
+    S hcolv[2] = {S(0), S(0)};
+    auto load_halo = [&](int set, int zz) {
+        hcolv[set] = hptr[(int64_t)zz * sz];
+#pragma unroll
+        for (int k = 0; k < NK; k++) {
+            const int i = kHaloJobs.e[wave + k * BY] >> 2;
+            hrow[set][k] = ld_at(sreg(base(f, i, zz) + (int64_t)yhk[k] * sy), xlb);
+        }
+    };
+    auto store_halo = [&](int set, TilePlane<BY, S>& T) {
+        if (hlane) T.v[hv][ty + 2][hcol] = hcolv[set];
 #pragma unroll
         for (int k = 0; k < NK; k++) {
             const int e = kHaloJobs.e[wave + k * BY];
             const int i = e >> 2, code = e & 3;
             const int r = code < 2 ? code - 2 : BY + code - 2;
-            const uint32_t yh = (uint32_t)min(y0 + r, g.ny + 1);
-            hrow[k] = (f + i * sv)[rowoff + yh * sy + zo];
+            T.v[i][r + 2][tx + 2] = hrow[set][k];
         }
     };
-    auto store_halo = [&]() {
-        if (hlane) P.v[hv][ty + 2][hcol] = hcolv;
-#pragma unroll
-        for (int k = 0; k < NK; k++) {
-            const int e = kHaloJobs.e[wave + k * BY];
-            const int i = e >> 2, code = e & 3;
-            const int r = code < 2 ? code - 2 : BY + code - 2;
-            P.v[i][r + 2][tx + 2] = hrow[k];
-        }
-    };
-    load_halo(z0);
 
-    // Every memory operation of the sweep is unconditional, so the
-    // compiler's wait counts stay exact (on this architecture loads and
-    // stores share one in-order counter): lanes outside the grid compute on
-    // clamped data and store to a sink element past the end of each velocity
-    // plane that is never read; the prefetch past the last plane is clamped.
-    const uint32_t sink = (uint32_t)g.sink;
+    // fixed-state x columns: the equilibrium of the face state, written
+    // into both planes once (lanes 0, 1: columns of layers -1, -2; lanes
+    // 2, 3: layers nx, nx+1)
+    {
+        const bool lfix = lf && kL == BC_INFLOW, rfix = rf && kR == BC_INFLOW;
+        if (lfix || rfix) {
+            const int side = tx >= 2 ? 1 : 0;
+            Macro<M> qf;
+            // (selects, not an index by `side`: a per-lane index would put
+            // the kernel argument in private memory)
+            qf.rho = static_cast<M>(side ? A.xin[1][0] : A.xin[0][0]);
+            qf.ux = static_cast<M>(side ? A.xin[1][1] : A.xin[0][1]);
+            qf.uy = static_cast<M>(side ? A.xin[1][2] : A.xin[0][2]);
+            qf.uz = static_cast<M>(side ? A.xin[1][3] : A.xin[0][3]);
+            qf.T = static_cast<M>(side ? A.xin[1][4] : A.xin[0][4]);
+            C e[NV];
+            equilibrium<C, M>(qf, mm, mc, e);
+            if (tx < 4 && (side ? rfix : lfix)) {
+                const int colw = tx == 0 ? 1 : tx == 1 ? 0 : tx + TILE_X;
+#pragma unroll
+                for (int i = 0; i < NV; i++) {
+                    P[0].v[i][ty + 2][colw] = static_cast<S>(e[i]);
+                    P[1].v[i][ty + 2][colw] = static_cast<S>(e[i]);
+                }
+            }
+        }
+    }
+    // layers of an extrapolating or reflecting x face of one plane from the
+    // moments of this row's two nodes next to the face, one value per lane:
+    // lane 32 s + 15 j + i (i < 15, j < 2) forms velocity i of layer j+1 of
+    // face s (0: -x, 1: +x) and writes it into the plane's halo column,
+    // which only this wavefront reads (so no barrier orders it)
+    auto form_x = [&](const Macro<M>& mq, TilePlane<BY, S>& T) {
+        const int side = tx >> 5, ll = tx & 31;
+        const int j = ll >= NV ? 1 : 0, iv = min(ll - NV * j, NV - 1);
+        const int kind = side ? kR : kL;
+        const bool on = ll < 2 * NV && (side ? rf : lf) && (kind == BC_OUTFLOW || kind == BC_REFLECT);
+        const Macro<M> q0 = shfl_macro(mq, side ? TILE_X - 1 : 0);
+        const Macro<M> q1 = shfl_macro(mq, side ? TILE_X - 2 : 1);
+        Macro<M> r1, r2, e1, e2;
+        reflect(q0, 0, r1, r2);
+        extrapolate(q0, q1, e1, e2);
+        const bool refl = kind == BC_REFLECT;
+        const Macro<M> qs = pick_macro(j == 0, pick_macro(refl, r1, e1), pick_macro(refl, r2, e2));
+        const C val = feq_vel<C>(iv, eq_coef<C, M>(qs, mm), mc);
+        if (on) T.v[iv][ty + 2][side ? TILE_X + 2 + j : 1 - j] = static_cast<S>(val);
+    };
+
+    // stage plane z0 in P[0]; the halo of plane z0+1 waits in set 1
+    load_halo(0, z0);
+    static_for<NV>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        P[0].v[I][ty + 2][tx + 2] = static_cast<S>(q[I][ring_slot<I>(0, 0)]);
+    });
+    store_halo(0, P[0]);
+    load_halo(1, zsel(z0 + 1));
+
     uint32_t hacc = 0;
-    // plane z0 is staged before the sweep; plane z+1 at the end of step z
-#pragma unroll
-    for (int i = 0; i < NV; i++) P.v[i][ty + 2][tx + 2] = static_cast<S>(q[i][1]);
-    store_halo();
-    for (int z = z0; z < z1; z++) {
-        const uint32_t zo = (uint32_t)z * sz;
-        // start the loads of the next plane's halo and of the planes ahead
-        C nxt[NV];
+    // one plane at unroll phase K: prefetch, barrier, compute from P[K & 1],
+    // stage plane z+1 in P[(K + 1) & 1]
+    auto plane = [&](auto kc, int z) {
+        constexpr int K = decltype(kc)::value;
+        TilePlane<BY, S>& cur = P[K & 1];
+        TilePlane<BY, S>& nxt = P[(K + 1) & 1];
         {
-            if (LBM3D_HALO_PREFETCH) load_halo(min(z + 1, g.nz));
-            const uint32_t o2 = col + (uint32_t)min(z + 2, g.nz + 1) * sz;
-            const uint32_t o3 = col + (uint32_t)min(z + 3, g.nz + 1) * sz;
-#pragma unroll
-            for (int i = 0; i < NV; i++) {
-                const S* fi = f + i * sv;
-                nxt[i] = static_cast<C>(fi[vsign(i, 2) < 0 ? o3 : o2]);
-            }
+            // planes z+2 (v_z >= 0) and z+3 (v_z < 0), walked velocity by velocity
+            const int za = zsel(z + 2);
+            const S* pa = base(f, 0, za);
+            const int64_t db = (int64_t)(zsel(z + 3) - za) * sz;
+            static_for<NV>([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                pa = sreg(pa);
+                const S* p = vsign(I, 2) < 0 ? sreg(pa + db) : pa;
+                q[I][(K + 3) & 3] = static_cast<C>(ld_at(p, colb));
+                pa += sv;
+            });
         }
+        load_halo(K & 1, zsel(z + 2));
         lds_barrier();
-        {
-            C fc[NV];
-#pragma unroll
-            for (int i = 0; i < NV; i++) fc[i] = q[i][1];
-            const Macro<M> mac = moments<M, C>(fc, mm);
-            hacc |= health_bits(mac);
-            C feq[NV];
-            equilibrium<C, M>(mac, mm, mc, feq);
-            const uint32_t out = act ? col + zo : sink;
-#pragma unroll
-            for (int i = 0; i < NV; i++) {
-                const int sx = vsign(i, 0), syy = vsign(i, 1), szz = vsign(i, 2), grp = vgroup(i);
-                const C vm = (grp == 1) ? mc.c1 : mc.k;
-                const C f0 = q[i][1];
-                const S* row = &P.v[i][ty + 2][tx + 2];
-                C xm1 = C(0), xp1 = C(0), ym1 = C(0), yp1 = C(0);
-                C conv = C(0);
-                if (sx != 0 || grp <= 1) {
-                    xm1 = static_cast<C>(row[-1]);
-                    xp1 = static_cast<C>(row[1]);
-                }
-                if (syy != 0 || grp <= 1) {
-                    ym1 = static_cast<C>(row[-(TILE_X + 4)]);
-                    yp1 = static_cast<C>(row[TILE_X + 4]);
-                }
-                if (sx > 0) conv += vm * nnd_diff<1, C>(static_cast<C>(row[-2]), xm1, f0, xp1, C(0));
-                if (sx < 0) conv -= vm * nnd_diff<-1, C>(C(0), xm1, f0, xp1, static_cast<C>(row[2]));
-                if (syy > 0)
-                    conv += vm * nnd_diff<1, C>(static_cast<C>(row[-2 * (TILE_X + 4)]), ym1, f0, yp1, C(0));
-                if (syy < 0)
-                    conv -= vm * nnd_diff<-1, C>(C(0), ym1, f0, yp1, static_cast<C>(row[2 * (TILE_X + 4)]));
-                if (szz > 0) {
-                    const C gz = face_pos(q[i][0], q[i][1], q[i][2]);
-                    conv += vm * (gz - gp[i]);
-                    gp[i] = gz;
-                }
-                if (szz < 0) {
-                    const C gz = face_neg(q[i][1], q[i][2], q[i][3]);
-                    conv -= vm * (gz - gp[i]);
-                    gp[i] = gz;
-                }
-                C ov = f0 - mc.k_adv * conv - mc.k_bgk * (f0 - feq[i]);
-                if (grp <= 1) {
-                    const C lap = ((xm1 + xp1) + (ym1 + yp1)) + (q[i][0] + q[i][2]) - C(6) * f0;
-                    ov += (grp == 0 ? mc.k_lap0 : mc.k_lap1) * lap;
-                }
-                (fn + i * sv)[out] = static_cast<S>(ov);
-            }
 
-        }
-        lds_barrier();
-#pragma unroll
-        for (int i = 0; i < NV; i++) {
-            q[i][0] = q[i][1];
-            q[i][1] = q[i][2];
-            if (vsign(i, 2) < 0) {
-                q[i][2] = q[i][3];
-                q[i][3] = nxt[i];
-            } else {
-                q[i][2] = nxt[i];
+        C fc[NV];
+        static_for<NV>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            fc[I] = q[I][ring_slot<I>(0, K)];
+        });
+        const Macro<M> mac = moments<M, C>(fc, mm);
+        hacc |= health_bits(mac);
+        // on tiles that form x layers (their own copy of the sweep, so no
+        // branch keeps the scheduler from interleaving it with the node's
+        // equilibrium) the layers of this plane come first
+        if constexpr (XF) form_x(mac, cur);
+        C feq[NV];
+        equilibrium<C, M>(mac, mm, mc, feq);
+        const uint32_t outb = act ? colb : (uint32_t)((sinkrel - (int64_t)z * sz) * ES);
+        S* po = wbase(fn, 0, z);
+        static_for<NV>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr int SX = vsign(I, 0), SY = vsign(I, 1), SZ = vsign(I, 2), G = vgroup(I);
+            constexpr int RW = TILE_X + 4;
+            const C f0 = fc[I];
+            const S* row = &cur.v[I][ty + 2][tx + 2];
+            C Dx = C(0), Dy = C(0), Dz = C(0), lx = C(0), ly = C(0), lz = C(0);
+            if constexpr (SX > 0) {
+                const C m2 = row[-2], m1 = row[-1], p1 = row[1];
+                const C e0 = f0 - m1, e1 = p1 - f0;
+                Dx = nnd_pos(m1 - m2, e0, e1);
+                lx = e1 - e0;
+            } else if constexpr (SX < 0) {
+                const C m1 = row[-1], p1 = row[1], p2 = row[2];
+                const C e0 = f0 - m1, e1 = p1 - f0;
+                Dx = nnd_neg(e0, e1, p2 - p1);
+                lx = e1 - e0;
+            } else if constexpr (G <= 1) {
+                lx = static_cast<C>(row[-1]) + static_cast<C>(row[1]);
             }
-        }
+            if constexpr (SY > 0) {
+                const C m2 = row[-2 * RW], m1 = row[-RW], p1 = row[RW];
+                const C e0 = f0 - m1, e1 = p1 - f0;
+                Dy = nnd_pos(m1 - m2, e0, e1);
+                ly = e1 - e0;
+            } else if constexpr (SY < 0) {
+                const C m1 = row[-RW], p1 = row[RW], p2 = row[2 * RW];
+                const C e0 = f0 - m1, e1 = p1 - f0;
+                Dy = nnd_neg(e0, e1, p2 - p1);
+                ly = e1 - e0;
+            } else if constexpr (G <= 1) {
+                ly = static_cast<C>(row[-RW]) + static_cast<C>(row[RW]);
+            }
+            if constexpr (SZ > 0) {
+                const C e0 = f0 - q[I][ring_slot<I>(-1, K)], e1 = q[I][ring_slot<I>(1, K)] - f0;
+                Dz = nnd_pos_c(e0, e1, mz[I]);
+                lz = e1 - e0;
+            } else if constexpr (SZ < 0) {
+                const C p1 = q[I][ring_slot<I>(1, K)];
+                const C e1 = p1 - f0;
+                Dz = nnd_neg_c(e1, q[I][ring_slot<I>(2, K)] - p1, mz[I]);
+                if constexpr (G == 1) {
+                    lz = e1 - ez6;
+                    ez6 = e1;
+                }
+            } else if constexpr (G <= 1) {
+                lz = q[I][ring_slot<I>(-1, K)] + q[I][ring_slot<I>(1, K)];
+            }
+            const C out = node_update<I, C>(f0, feq[I], Dx, Dy, Dz, lx, ly, lz, mc);
+            po = sreg(po);
+            st_at(po, outb, static_cast<S>(out));
+            po += sv;
+        });
+
         // stage plane z+1: own values and its halo
-#pragma unroll
-        for (int i = 0; i < NV; i++) P.v[i][ty + 2][tx + 2] = static_cast<S>(q[i][1]);
-        if (!LBM3D_HALO_PREFETCH) load_halo(min(z + 1, g.nz));
-        store_halo();
-    }
-    if (act && hacc) atomicOr(A.health, hacc);
+        static_for<NV>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            nxt.v[I][ty + 2][tx + 2] = static_cast<S>(q[I][ring_slot<I>(1, K)]);
+        });
+        store_halo((K + 1) & 1, nxt);
+    };
 
-    // ---- boundary layers of the new level (Sec. 4 (2)).  After the sweep,
-    // the tile writes the layers whose source nodes it owns, as dense "line
-    // jobs" spread over all its threads: one job is one line of nodes
-    // perpendicular to a face; it reads back the one or two new nodes next
-    // to the face (written above by this workgroup; the barrier makes them
-    // visible) and writes the two layer nodes.  Edges and corners of the
-    // layers are never read.
-#if !LBM3D_FUSE_LAYERS
-    if (act && hacc) atomicOr(A.health, hacc);
-    return;
-#else
-    const int zc = z1 - z0;
-    const int xe = min(x0 + TILE_X, g.nx), ye = min(y0 + BY, g.ny);
-    bool work[6];
-#pragma unroll
-    for (int face = 0; face < 6; face++) {
-        const int axis = face >> 1;
-        const int lo = axis == 0 ? x0 : axis == 1 ? y0 : z0;
-        const int hi = axis == 0 ? xe : axis == 1 ? ye : z1;  // tile owns nodes [lo, hi) along axis
-        const int n = axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz;
-        work[face] = ((A.fused >> face) & 1) && layer_owner(A.bc.kind[face], face & 1, n, lo, hi);
-    }
-    if (!(work[0] || work[1] || work[2] || work[3] || work[4] || work[5])) {
-        if (act && hacc) atomicOr(A.health, hacc);
-        return;
+    for (int z = z0;;) {
+        plane(std::integral_constant<int, 0>{}, z);
+        if (++z >= z1) break;
+        plane(std::integral_constant<int, 1>{}, z);
+        if (++z >= z1) break;
+        plane(std::integral_constant<int, 2>{}, z);
+        if (++z >= z1) break;
+        plane(std::integral_constant<int, 3>{}, z);
+        if (++z >= z1) break;
     }
     if (act && hacc) atomicOr(A.health, hacc);
-    __syncthreads();
-    const int nthr = TILE_X * BY;
-#pragma unroll
-    for (int face = 0; face < 6; face++) {
-        if (!work[face]) continue;
-        const int axis = face >> 1;
-        // lines of this face inside the tile: the two other coordinates
-        const int cnt = axis == 0 ? (ye - y0) * zc : axis == 1 ? (xe - x0) * zc : (xe - x0) * (ye - y0);
-        for (int j = threadIdx.x; j < cnt; j += nthr) {
-            int cx = 0, cy = 0, cz = 0;
-            if (axis == 0) { cy = y0 + j % (ye - y0); cz = z0 + j / (ye - y0); }
-            else if (axis == 1) { cx = x0 + j % (xe - x0); cz = z0 + j / (xe - x0); }
-            else { cx = x0 + j % (xe - x0); cy = y0 + j / (xe - x0); }
-            const uint32_t line = (uint32_t)(g.org + (int64_t)cz * g.sz + (int64_t)cy * g.sy + cx);
-            const uint32_t st = axis == 0 ? 1u : axis == 1 ? sy : sz;
-            const int n = axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz;
-            const int lo = axis == 0 ? x0 : axis == 1 ? y0 : z0;
-            const int hi = axis == 0 ? xe : axis == 1 ? ye : z1;
-            layer_line<MODE>(A, mm, mc, face, line, st, n, lo, hi);
-        }
-    }
-#endif
 }
 
-// Tile order: tiles are numbered with y fastest, then x, then the z chunk,
-// and consecutive numbers are given to workgroups that land on the same
-// XCD (dispatch assigns workgroup b to XCD b mod 8), so that tiles sharing
-// halo rows share an L2.
+// Does the tile at x0 form extrapolating or reflecting x layers itself?
+template <int MODE>
+__device__ __forceinline__ bool x_forms(const StepArgs<MODE>& A, int x0)
+{
+    if (!LBM3D_X_IN_TILE || (A.g.nx % TILE_X) != 0) return false;
+    auto formed = [](int k) { return k == BC_OUTFLOW || k == BC_REFLECT; };
+    return (x0 == 0 && formed(A.bc.kind[0])) || (x0 + TILE_X == A.g.nx && formed(A.bc.kind[1]));
+}
+
+template <int MODE, int BY>
+__device__ __forceinline__ void step_tile(const StepArgs<MODE>& A, const Model<double>& md,
+                                          const Model<float>& mf, int x0, int y0, int z0, int z1,
+                                          TilePlane<BY, typename Types<MODE>::S> (&P)[2])
+{
+    if (x_forms(A, x0))
+        step_tile_x<MODE, BY, true>(A, md, mf, x0, y0, z0, z1, P);
+    else
+        step_tile_x<MODE, BY, false>(A, md, mf, x0, y0, z0, z1, P);
+}
+
+// Tile order: tiles are numbered with x (or y) fastest, then the other
+// axis, then the z chunk, and consecutive numbers are given to workgroups
+// that land on the same XCD (dispatch assigns workgroup b to XCD b mod 8),
+// so that tiles sharing halo rows and columns share an L2.
 __device__ __forceinline__ int xcd_tile(int b, int nblocks)
 {
     const int per = nblocks >> 3, rem = nblocks & 7;

@@ -21,6 +21,8 @@ def _mix(precision):
         inputs.riemann_3d(3, grid=(70, 19, 13), precision=precision),
         inputs.shock_bubble(4, grid=(65, 21, 17), precision=precision, mach=6.0, ratio=4.0),
         inputs.smooth_periodic(5, grid=(20, 12, 9), precision=precision),
+        inputs.shock_bubble(6, grid=(128, 24, 16), precision=precision, mach=2.5, ratio=0.5),
+        inputs.riemann_3d(7, grid=(64, 19, 11), precision=precision),
     ]
 
 
@@ -37,7 +39,7 @@ def _alone(case, steps):
 def test_batch_equals_alone_bitwise(precision):
     lbm3d = _lib()
     cases = _mix(precision)
-    steps = [40, 23, 40, 1, 17]
+    steps = [40, 23, 40, 1, 17, 30, 12]
     solvers = []
     for c in cases:
         s = lbm3d.Solver(dict(c.params))

@@ -74,6 +74,14 @@ def _small_cases():
     c = inputs.smooth_periodic(10, grid=(2, 64, 2), amp=0.3)
     c.params = dict(c.params, bc=(3, 3, 1, 1, 3, 3))
     out.append(("min_sizes_2x64x2", c, 30))
+    # x covered exactly by 64-wide tiles: the tiled kernel forms the x layers
+    # itself (fixed state, extrapolation, reflection) or wraps them
+    sb = inputs.shock_bubble(12, grid=(128, 20, 12), precision="fp64", mach=5.0, ratio=3.0)
+    out.append(("shockbubble_128x20x12_xlayers", sb, 30))
+    c = inputs.smooth_periodic(13, grid=(64, 19, 13), amp=0.3)
+    c.params = dict(c.params, bc=(3, 1, 0, 0, 0, 0))
+    out.append(("reflect_outflow_64x19x13_yz_wrap", c, 40))
+    out.append(("periodic_128x9x7_wrap", inputs.smooth_periodic(14, grid=(128, 9, 7), amp=0.3), 40))
     return out
 
 
@@ -219,12 +227,26 @@ def test_step_before_init_is_rejected():
     assert ei.value.code == lbm3d.E_INVAL
 
 
+def _tile_cases(precision):
+    out = [inputs.shock_bubble(11, grid=(70, 19, 13), precision=precision, mach=3.0, ratio=0.4),
+           inputs.shock_bubble(11, grid=(128, 19, 13), precision=precision, mach=3.0, ratio=0.4)]
+    c = inputs.smooth_periodic(15, grid=(64, 21, 11), amp=0.3, precision=precision)
+    c.params = dict(c.params, bc=(1, 3, 0, 0, 0, 0))
+    out.append(c)
+    c = inputs.smooth_periodic(16, grid=(128, 12, 9), amp=0.3, precision=precision)
+    c.params = dict(c.params, bc=(0, 0, 3, 1, 1, 3))
+    out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("which", range(4))
 @pytest.mark.parametrize("precision", ["fp64", "fp32_t64"])
-def test_results_do_not_depend_on_tile_shape(precision):
+def test_results_do_not_depend_on_tile_shape(precision, which):
     """Every launch shape (untiled, and 64 x BY x TZ tiles with ragged edges
-    in x, y and z) gives bitwise the same distributions."""
+    in x, y and z) gives bitwise the same distributions, whether the tiles
+    read the boundary layers from memory or form / wrap them themselves."""
     lbm3d = _lib()
-    case = inputs.shock_bubble(11, grid=(70, 19, 13), precision=precision, mach=3.0, ratio=0.4)
+    case = _tile_cases(precision)[which]
     shapes = [(0, 1), (2, 1), (2, 5), (4, 3), (4, 16)]
     if precision != "fp64":
         shapes += [(8, 2), (8, 13)]
@@ -241,3 +263,20 @@ def test_results_do_not_depend_on_tile_shape(precision):
             ref = f
         else:
             assert np.array_equal(f, ref), (by, tz)
+
+
+def test_switching_launch_shape_mid_run():
+    """A tiled run that hands over to the untiled kernel part way (layers the
+    tiles formed themselves are refreshed in memory) matches an untiled run."""
+    lbm3d = _lib()
+    case = inputs.shock_bubble(17, grid=(128, 19, 13), precision="fp64", mach=4.0, ratio=0.3)
+    a = lbm3d.Solver(dict(case.params))
+    a.set_tile(0, 1)
+    a.init(*case.fields)
+    a.step(20)
+    b = lbm3d.Solver(dict(case.params))
+    b.init(*case.fields)
+    b.step(10)
+    b.set_tile(0, 1)
+    b.step(10)
+    assert np.array_equal(a.get_f(), b.get_f())
