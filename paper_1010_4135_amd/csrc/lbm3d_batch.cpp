@@ -17,6 +17,10 @@ static int32_t herr(hipError_t e)
 
 // Steps per captured graph of the batched step (even: parities 0,1,...).
 constexpr int BATCH_GRAPH_STEPS = 16;
+// z extent of a batch tile (build-time tuning knob)
+#ifndef LBM3D_BATCH_TZ
+#define LBM3D_BATCH_TZ 16
+#endif
 
 BatchPlan::~BatchPlan()
 {
@@ -40,7 +44,7 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     if (members.empty()) return LBM3D_OK;
     mode_ = members[0]->mode;
     by_ = mode_ == LBM3D_FP64 ? 4 : 8;
-    tz_ = 8;
+    tz_ = LBM3D_BATCH_TZ;
 
     // packed tile list: each solve's tiles in (z chunk, y, x) order, split
     // into eight contiguous runs interleaved so that run c lands on XCD c
@@ -96,11 +100,36 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
             cus = prop.multiProcessorCount;
     }
-    nblocks_ = std::min(n, cus * 3);
+    // (one workgroup per CU is what the LDS of a tile leaves room for)
+    nblocks_ = std::min(n, cus);
     if (nblocks_ >= 8) nblocks_ -= nblocks_ % 8;
 
+    // boundary layers left after each step: one launch over all members
+    std::vector<BatchLayerJob> ljobs;
+    nlblocks_ = 0;
+    for (size_t k = 0; k < members.size(); k++) {
+        const uint32_t faces = ghost_rest_[k];
+        if (!faces) continue;
+        const Grid& g = members[k]->g;
+        int64_t lines = 0;
+        for (int face = 0; face < 6; face++) {
+            if (!((faces >> face) & 1)) continue;
+            const int axis = face >> 1;
+            lines += axis == 0 ? (int64_t)g.ny * g.nz : axis == 1 ? (int64_t)g.nx * g.nz : (int64_t)g.nx * g.ny;
+        }
+        BatchLayerJob jb;
+        jb.solve = (int32_t)k;
+        jb.faces = faces;
+        jb.first = nlblocks_;
+        ljobs.push_back(jb);
+        nlblocks_ += (int)((lines + 63) / 64);
+    }
+    nljobs_ = (int)ljobs.size();
+
     const size_t sb = table.size() * sizeof(BatchSolve);
-    const size_t need = sb + (size_t)n * sizeof(BatchTile) + 256;
+    const size_t tb = (size_t)n * sizeof(BatchTile);
+    const size_t lb = ljobs.size() * sizeof(BatchLayerJob);
+    const size_t need = ((sb + 255) / 256) * 256 + ((tb + 255) / 256) * 256 + lb + 256;
     if (need > dbytes_) {
         if (dmem_) (void)hipFree(dmem_);
         dmem_ = nullptr;
@@ -111,9 +140,10 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     }
     dsolves_ = (BatchSolve*)dmem_;
     dtiles_ = (BatchTile*)((char*)dmem_ + ((sb + 255) / 256) * 256);
+    dlayers_ = (BatchLayerJob*)((char*)dtiles_ + ((tb + 255) / 256) * 256);
     hipError_t e = hipMemcpyAsync(dsolves_, table.data(), sb, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(dtiles_, tiles.data(), (size_t)n * sizeof(BatchTile), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dtiles_, tiles.data(), tb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && lb) e = hipMemcpyAsync(dlayers_, ljobs.data(), lb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables die at return
     return herr(e);
 }
@@ -122,15 +152,8 @@ hipError_t BatchPlan::enqueue(int parity, hipStream_t s)
 {
     hipError_t e = launch_batch_step(mode_, by_, dsolves_, dtiles_, ntiles_, nblocks_, parity, s);
     if (e != hipSuccess) return e;
-    // faces whose layers the step cannot write (rare): the boundary kernel
-    for (size_t k = 0; k < members_.size(); k++) {
-        if (!ghost_rest_[k]) continue;
-        lbm3d_solver* h = members_[k];
-        const int cur = cur0_[k] ^ parity;
-        e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[cur ^ 1], s, ghost_rest_[k]);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    // boundary layers the tiles do not form themselves, all members at once
+    return launch_batch_layers(mode_, dsolves_, dlayers_, nljobs_, nlblocks_, parity, s);
 }
 
 int32_t BatchPlan::run(int64_t k, hipStream_t s)

@@ -36,7 +36,9 @@ private:
     size_t dbytes_ = 0;
     BatchSolve* dsolves_ = nullptr;
     BatchTile* dtiles_ = nullptr;
-    std::vector<uint32_t> ghost_rest_;  // per member: faces left to the boundary kernel
+    BatchLayerJob* dlayers_ = nullptr;  // boundary-layer jobs (sorted by first workgroup)
+    int nljobs_ = 0, nlblocks_ = 0;
+    std::vector<uint32_t> ghost_rest_;  // per member: faces left to the boundary-layer launch
     std::vector<int> cur0_;             // per member: current buffer at build()
     hipGraphExec_t graph_ = nullptr;
     hipStream_t capture_stream_ = nullptr;

@@ -185,14 +185,14 @@ struct FixedStates {
     double q[6][5];  // (rho, ux, uy, uz, T) per fixed-state face
 };
 
+// Line j (over the selected faces in order) of one solve's boundary layers.
 template <int MODE>
-__global__ void __launch_bounds__(64)
-k_layers(StepArgs<MODE> A, Model<double> md, Model<float> mf, FixedStates fx, uint32_t faces)
+__device__ __forceinline__ void layer_job(const StepArgs<MODE>& A, const Model<double>& md, const Model<float>& mf,
+                                          const FixedStates* fx, uint32_t faces, int64_t j)
 {
     using C = typename Types<MODE>::C;
     using M = typename Types<MODE>::M;
     const Grid& g = A.g;
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 #pragma unroll
     for (int face = 0; face < 6; face++) {
         if (!((faces >> face) & 1)) continue;
@@ -210,12 +210,13 @@ k_layers(StepArgs<MODE> A, Model<double> md, Model<float> mf, FixedStates fx, ui
         const uint32_t st = axis == 0 ? 1u : axis == 1 ? (uint32_t)g.sy : (uint32_t)g.sz;
         const int n = axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz;
         if (A.bc.kind[face] == BC_INFLOW) {
+            if (!fx) return;
             Macro<M> q;
-            q.rho = static_cast<M>(fx.q[face][0]);
-            q.ux = static_cast<M>(fx.q[face][1]);
-            q.uy = static_cast<M>(fx.q[face][2]);
-            q.uz = static_cast<M>(fx.q[face][3]);
-            q.T = static_cast<M>(fx.q[face][4]);
+            q.rho = static_cast<M>(fx->q[face][0]);
+            q.ux = static_cast<M>(fx->q[face][1]);
+            q.uy = static_cast<M>(fx->q[face][2]);
+            q.uz = static_cast<M>(fx->q[face][3]);
+            q.T = static_cast<M>(fx->q[face][4]);
             C e[NV];
             equilibrium<C, M>(q, pick<M>(md, mf), pick<C>(md, mf), e);
             const int side = face & 1;
@@ -226,6 +227,40 @@ k_layers(StepArgs<MODE> A, Model<double> md, Model<float> mf, FixedStates fx, ui
         }
         return;
     }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(64)
+k_layers(StepArgs<MODE> A, Model<double> md, Model<float> mf, FixedStates fx, uint32_t faces)
+{
+    layer_job<MODE>(A, md, mf, &fx, faces, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Boundary layers of many solves in one launch: job k covers workgroups
+// [first[k], first[k+1]) of solve jobs[k].solve (faces jobs[k].faces), so
+// each workgroup finds its job by a binary search over the sorted table.
+template <int MODE>
+__global__ void __launch_bounds__(64)
+k_layers_batch(const BatchSolve* __restrict__ solves, const BatchLayerJob* __restrict__ jobs, int njobs, int parity)
+{
+    using S = typename Types<MODE>::S;
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].first <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchLayerJob jb = jobs[lo];
+    const BatchSolve& d = solves[jb.solve];
+    StepArgs<MODE> A;
+    A.g = d.g;
+    A.bc = d.bc;
+    const int cur = d.cur0 ^ parity;
+    A.f = nullptr;
+    A.fn = (S*)d.f[cur ^ 1];
+    A.health = nullptr;
+    layer_job<MODE>(A, d.md, d.mf, nullptr, jb.faces, (int64_t)(b - jb.first) * 64 + threadIdx.x);
 }
 
 // -------------------------------------------------------------- moments --
@@ -539,6 +574,14 @@ hipError_t launch_pack(int mode, const Grid& g, const void* f, void* dense, bool
     else
         hipLaunchKernelGGL(k_pack<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, (float*)f,
                            (float*)dense, to_dense ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLayerJob* jobs, int njobs, int nblocks,
+                               int parity, hipStream_t s)
+{
+    if (njobs <= 0 || nblocks <= 0) return hipSuccess;
+    LBM3D_DISPATCH(mode, k_layers_batch<MD><<<dim3(nblocks), dim3(64), 0, s>>>(solves, jobs, njobs, parity));
     return hipGetLastError();
 }
 

@@ -67,6 +67,14 @@ struct BatchSolve {
     Model<float> mf;
 };
 
+// One solve's share of the batched boundary-layer launch: workgroups
+// [first, next job's first) of 64 lines each over the faces in `faces`.
+struct BatchLayerJob {
+    int32_t solve;
+    uint32_t faces;
+    int32_t first;
+};
+
 // ---- launches (lbm3d_device.hip) ----
 hipError_t launch_init(int mode, const Grid& g, const Model<double>& md, const double* q5,
                        void* f, hipStream_t s);
@@ -104,6 +112,9 @@ hipError_t launch_pack(int mode, const Grid& g, const void* f, void* dense, bool
                        hipStream_t s);
 // One step of every solve in `solves` (device table) over the packed tile
 // list (device); `parity` selects f[cur0 ^ parity] as the current level.
+// Boundary layers of the members of a batch after a step (one launch).
+hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLayerJob* jobs, int njobs, int nblocks,
+                               int parity, hipStream_t s);
 hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles, int ntiles,
                              int nblocks, int parity, hipStream_t s);
 
