@@ -334,6 +334,8 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     const bool ywrap = LBM3D_WRAP_YZ && A.bc.kind[2] == BC_PERIODIC;
     const bool zwrap = LBM3D_WRAP_YZ && A.bc.kind[4] == BC_PERIODIC;
     auto zsel = [&](int zz) { return zwrap ? wrap_idx(zz, g.nz) : min(zz, zmax); };
+    // the plane after zz (wrapped or clamped like zsel), without a division
+    auto znext = [&](int zz) { return zwrap ? (zz + 1 == g.nz ? 0 : zz + 1) : min(zz + 1, zmax); };
     const int xl = min(x, g.nx + 1);
     const int yl = ywrap ? wrap_idx(min(y, g.ny + 9), g.ny) : min(y, g.ny + 1);
     // uniform base of velocity i at plane zz (node (0, 0, zz))
@@ -481,6 +483,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     load_halo(1, zsel(z0 + 1));
 
     uint32_t hacc = 0;
+    int za = zsel(z0 + 2), zb = zsel(z0 + 3);  // planes z+2 and z+3 of the current step
     // one plane at unroll phase K: prefetch, barrier, compute from P[K & 1],
     // stage plane z+1 in P[(K + 1) & 1]
     auto plane = [&](auto kc, int z) {
@@ -489,9 +492,8 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
         TilePlane<BY, S>& nxt = P[(K + 1) & 1];
         {
             // planes z+2 (v_z >= 0) and z+3 (v_z < 0), walked velocity by velocity
-            const int za = zsel(z + 2);
             const S* pa = base(f, 0, za);
-            const int64_t db = (int64_t)(zsel(z + 3) - za) * sz;
+            const int64_t db = (int64_t)(zb - za) * sz;
             static_for<NV>([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 pa = sreg(pa);
@@ -500,7 +502,9 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
                 pa += sv;
             });
         }
-        load_halo(K & 1, zsel(z + 2));
+        load_halo(K & 1, za);
+        za = znext(za);
+        zb = znext(zb);
         lds_barrier();
 
         C fc[NV];
