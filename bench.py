@@ -17,6 +17,9 @@ Beside it:
                 `traffic` is the counter-measured HBM bytes per launch from
                 the committed rocprofv3 summary when it was taken on this
                 kernel source, else null;
+  periodic_riemann  the 128^3 periodic 3D Riemann problem in FP64, FP32 and
+                FP32 with FP64 temperature: MLUPS, kernel GB/s and the FP32
+                modes' error against the FP64 run;
   batch         64 solves of uneven size, 500 steps each, in one persistent
                 launch per step vs the same solves stepped one after another;
   serving       an open Poisson stream of mixed solves through the
@@ -111,6 +114,7 @@ def batch_bench(lbm3d, inputs, seed: int, count: int = 64, steps: int = 500):
         return out
 
     solvers = fresh()
+    tz = lbm3d.lbm3d_batch_tune([s.h for s in solvers], 5)  # tile depth from the autotuner
     lbm3d.lbm3d_batch_step([s.h for s in solvers], [1] * count)  # warm-up (plan, graph, code)
     t0 = time.perf_counter()
     lbm3d.lbm3d_batch_step([s.h for s in solvers], [steps] * count)
@@ -131,10 +135,38 @@ def batch_bench(lbm3d, inputs, seed: int, count: int = 64, steps: int = 500):
     for s in solvers:
         s.close()
     return {"solves": count, "steps_each": steps, "sites_total": sites, "precision": "fp32_t64",
+            "tile": [64, 8, tz], "tile_from": "autotuner",
             "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
             "batched_mlups": round(sites * steps / t_batch / 1e6, 1),
             "sequential_mlups": round(sites * steps / t_seq / 1e6, 1),
             "speedup": round(t_seq / t_batch, 3), "first4_bitwise_equal_alone": bool(same)}
+
+
+def periodic_riemann_bench(lbm3d, inputs, metrics, seed: int, steps: int = 200):
+    """128^3 periodic 3D Riemann problem in each precision: MLUPS, the step
+    kernel's algorithmic GB/s, and the FP32 modes' per-field relative L1
+    distance to the FP64 run after the same steps (the FP64 mode itself is
+    held to the FP64 oracle by the parity tests)."""
+    out = {"workload": "riemann_3d 128^3 periodic", "steps": steps}
+    ref = None
+    for prec in ("fp64", "fp32", "fp32_t64"):
+        case = inputs.riemann_3d(seed, precision=prec)
+        s = lbm3d.Solver(case.params)
+        s.init(*case.fields)
+        s.tune(5)
+        ms = s.step_timed(steps)
+        m = s.moments()  # after exactly `steps` steps in every precision
+        _, kms = s.step_profiled(20)
+        bps = BYTES_PER_SITE[prec]
+        s.close()
+        row = {"mlups": round(case.sites * steps / (ms / 1e3) / 1e6, 1),
+               "kernel_gbs": round(case.sites * bps / (kms / 1e3) / 1e9, 1)}
+        if prec == "fp64":
+            ref = m
+        else:
+            row["rel_l1_vs_fp64"] = {k: float(f"{v:.3e}") for k, v in metrics.rel_l1(m, ref).items()}
+        out[prec] = row
+    return out
 
 
 def _pct(v, q):
@@ -221,6 +253,10 @@ def main():
     nx, ny, nz = case.grid
     s = lbm3d.Solver(case.params)
     s.init(*case.fields)
+    # launch shape from the autotuner (state unchanged; outside the timed region)
+    t_tune = time.perf_counter()
+    s.tune(10)
+    t_tune = time.perf_counter() - t_tune
     s.step(args.warmup)
     s.sync()
     # timed region: K steps replayed from captured graphs, HIP events on the
@@ -257,7 +293,8 @@ def main():
                         (" (FP32 f, FP64 temperature recovery)" if args.precision == "fp32_t64" else ""),
             "grid": [nx, ny, nz], "precision": args.precision, "seed": args.seed,
             "mach": round(case.meta["mach"], 4), "density_ratio": round(case.meta["ratio"], 4),
-            "tile": [64, by, tz], "wall_s_timed_region": round(wall, 4), "health": health, "steps_done": done,
+            "tile": [64, by, tz], "tile_from": "autotuner", "tune_s": round(t_tune, 3),
+            "wall_s_timed_region": round(wall, 4), "health": health, "steps_done": done,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -268,6 +305,7 @@ def main():
     }
     s.close()
     if not args.no_batch:
+        out["periodic_riemann"] = periodic_riemann_bench(lbm3d, inputs, metrics, args.seed)
         out["batch"] = batch_bench(lbm3d, inputs, args.seed)
     if not args.no_serve:
         out["serving"] = serve_bench(lbm3d, inputs, metrics, args.seed)

@@ -152,6 +152,16 @@ int32_t lbm3d_step_profiled(lbm3d_t h, int64_t nsteps, double* total_ms, double*
 int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz);
 int32_t lbm3d_get_tile(lbm3d_t h, int32_t* by, int32_t* tz);
 
+/* Autotuner of the launch shape.  Times every supported tile shape (and the
+ * untiled kernel) over `launches` launches each (<= 0: 10), with HIP events
+ * on the solver's stream, by stepping from the current level into the other
+ * buffer again and again; the solve's state and step count are unchanged.
+ * Keeps the fastest shape (as lbm3d_set_tile) and remembers it for the
+ * process: later lbm3d_create calls for the same precision, grid and
+ * boundary kinds start with it.  Blocking.  by / tz (may be NULL) receive
+ * the shape.  E_STATE before lbm3d_init. */
+int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t* tz);
+
 /* Wait for all work enqueued on the handle's stream. */
 int32_t lbm3d_sync(lbm3d_t h);
 
@@ -189,6 +199,14 @@ int32_t lbm3d_set_f(lbm3d_t h, const void* host, size_t bytes);
  * or a solve whose velocity plane (about nx*ny*nz elements) reaches 2 GiB:
  * the batched kernel addresses a plane with 32-bit offsets. */
 int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* nsteps);
+
+/* Autotuner of the batched step: times the persistent launch over the given
+ * solves (same rules as lbm3d_batch_step) for tile depths 8, 16 and 32, over
+ * `launches` launches each (<= 0: 5), recomputing the same next level each
+ * time (states unchanged), and keeps the fastest depth for every later
+ * batched step (lbm3d_batch_step and servers) of that precision in this
+ * process.  Blocking.  *tz (may be NULL) receives the depth. */
+int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches, int32_t* tz);
 
 /* ------------------------------------------------------------- serving --- */
 typedef struct lbm3d_server* lbm3d_server_t;

@@ -203,6 +203,8 @@ int32_t solver_create(const lbm3d_params* p, lbm3d_solver** out)
     h->mf = model_to_float(h->md);
     for (int f = 0; f < 6; f++) h->bc.kind[f] = p->bc[f];
     h->tile = default_tile(h->mode, h->g);
+    TileCfg tuned;
+    if (cached_tile(h->mode, h->g, h->bc, &tuned) && tile_supported(h->mode, h->g, tuned)) h->tile = tuned;
     h->n = (int64_t)p->nx * p->ny * p->nz;
     const size_t fb = f_bytes(h->g, h->mode);
     h->nred = conserved_blocks(h->g);

@@ -45,5 +45,9 @@ size_t f_bytes(const Grid& g, int precision);
 size_t footprint_of(const lbm3d_params* p);
 int32_t solver_create(const lbm3d_params* p, lbm3d_solver** out);
 int32_t solver_enqueue_steps(lbm3d_solver* h, int64_t nsteps);
+// autotuner results (lbm3d_tune.cpp): the tuned tile of a solve shape, and
+// the tuned batch tile depth of a precision (0 if not tuned)
+bool cached_tile(int mode, const Grid& g, const FaceBC& bc, TileCfg* out);
+int batch_tile_depth(int mode);
 
 }  // namespace lbm3d

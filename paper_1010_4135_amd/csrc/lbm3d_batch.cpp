@@ -35,7 +35,7 @@ void BatchPlan::release_graph()
     graph_ = nullptr;
 }
 
-int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t s)
+int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t s, int tz)
 {
     release_graph();
     members_ = members;
@@ -44,7 +44,9 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     if (members.empty()) return LBM3D_OK;
     mode_ = members[0]->mode;
     by_ = mode_ == LBM3D_FP64 ? 4 : 8;
-    tz_ = LBM3D_BATCH_TZ;
+    // tile depth: the caller's, else the tuned one, else the build default
+    tz_ = tz > 0 ? tz : batch_tile_depth(mode_);
+    if (tz_ <= 0) tz_ = LBM3D_BATCH_TZ;
 
     // packed tile list: each solve's tiles in (z chunk, y, x) order, split
     // into eight contiguous runs interleaved so that run c lands on XCD c
@@ -147,6 +149,8 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables die at return
     return herr(e);
 }
+
+hipError_t BatchPlan::launch_once(hipStream_t s) { return enqueue(0, s); }
 
 hipError_t BatchPlan::enqueue(int parity, hipStream_t s)
 {

@@ -19,7 +19,12 @@ public:
 
     // (Re)build for `members` (all initialised, same precision); each
     // member's current buffer is taken as parity 0.  Enqueued on `s`.
-    int32_t build(const std::vector<lbm3d_solver*>& members, hipStream_t s);
+    // `tz` > 0 sets the tile depth, else the tuned or default one is used.
+    int32_t build(const std::vector<lbm3d_solver*>& members, hipStream_t s, int tz = 0);
+    // One step of every member from the build-time buffers into the other
+    // ones, without advancing anything (for timing: repeated launches
+    // recompute the same next level).
+    hipError_t launch_once(hipStream_t s);
     // Enqueue k steps of every member on `s` and update the members'
     // buffer parity and step counters.
     int32_t run(int64_t k, hipStream_t s);

@@ -1,0 +1,174 @@
+// Autotuner of the launch shapes: the fused step's tile (64 x BY x TZ) of a
+// single solve and the tile depth of the batched step.  Each candidate is
+// timed with HIP events on the solve's own data, launching the step from
+// the current buffer into the other one again and again (the current level
+// is never overwritten, so the state of the solves is unchanged), and the
+// fastest shape is kept and remembered for later solves of the same shape.
+#include "lbm3d_api_impl.h"
+#include "lbm3d_batch.h"
+
+#include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
+#include <set>
+#include <vector>
+
+namespace lbm3d {
+namespace {
+
+struct ShapeKey {
+    std::array<int, 10> v;  // precision, nx, ny, nz, six boundary kinds
+    bool operator<(const ShapeKey& o) const { return v < o.v; }
+};
+
+ShapeKey key_of(int mode, const Grid& g, const FaceBC& bc)
+{
+    ShapeKey k;
+    k.v = {mode, g.nx, g.ny, g.nz, bc.kind[0], bc.kind[1], bc.kind[2], bc.kind[3], bc.kind[4], bc.kind[5]};
+    return k;
+}
+
+std::mutex g_mu;
+std::map<ShapeKey, TileCfg> g_tiles;  // tuned tile per solve shape
+int g_batch_tz[3] = {0, 0, 0};        // tuned batch tile depth per precision (0: not tuned)
+
+std::vector<TileCfg> tile_candidates(int mode, const Grid& g)
+{
+    std::vector<TileCfg> c;
+    TileCfg u;
+    u.by = 0;
+    u.tz = 1;
+    c.push_back(u);
+    const int bys[3] = {2, 4, 8};
+    const int tzs[5] = {8, 16, 32, 64, 128};
+    for (int by : bys)
+        for (int tz : tzs) {
+            TileCfg t;
+            t.by = by;
+            t.tz = tz;
+            if (tz > 2 * std::max(g.nz, 1) && tz != tzs[0]) continue;  // deeper than the grid adds nothing
+            if (tile_supported(mode, g, t)) c.push_back(t);
+        }
+    return c;
+}
+
+}  // namespace
+
+bool cached_tile(int mode, const Grid& g, const FaceBC& bc, TileCfg* out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tiles.find(key_of(mode, g, bc));
+    if (it == g_tiles.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+int batch_tile_depth(int mode)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return (mode >= 0 && mode < 3) ? g_batch_tz[mode] : 0;
+}
+
+}  // namespace lbm3d
+
+using namespace lbm3d;
+
+static int32_t herr2(hipError_t e)
+{
+    return e == hipSuccess ? LBM3D_OK : (e == hipErrorOutOfMemory ? LBM3D_E_NOMEM : LBM3D_E_DEVICE);
+}
+
+extern "C" int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t* tz)
+{
+    if (!h) return LBM3D_E_INVAL;
+    if (!h->initialised) return LBM3D_E_STATE;
+    if (launches <= 0) launches = 10;
+    hipStream_t s = h->stream;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return herr2(e);
+    const void* f = h->f[h->cur];
+    void* fn = h->f[h->cur ^ 1];  // the next level's buffer: free until the next step
+    TileCfg best = h->tile;
+    float best_ms = -1.0f;
+    for (const TileCfg& t : tile_candidates(h->mode, h->g)) {
+        auto launch = [&]() {
+            return launch_step(h->mode, h->g, h->bc, t, h->md, h->mf, h->p.inflow, f, fn, h->health, s);
+        };
+        for (int w = 0; w < 2 && e == hipSuccess; w++) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(h->ev0, s);
+        for (int k = 0; k < launches && e == hipSuccess; k++) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(h->ev1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->ev0, h->ev1);
+        if (e != hipSuccess) return herr2(e);
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    int32_t rc = lbm3d_set_tile(h, best.by, best.tz);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tiles[key_of(h->mode, h->g, h->bc)] = best;
+    }
+    if (by) *by = best.by;
+    if (tz) *tz = best.tz;
+    return LBM3D_OK;
+}
+
+extern "C" int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches, int32_t* tz)
+{
+    if (!hs || count < 1) return LBM3D_E_INVAL;
+    std::set<lbm3d_t> seen;
+    for (int32_t k = 0; k < count; k++) {
+        if (!hs[k] || !seen.insert(hs[k]).second) return LBM3D_E_INVAL;
+        if (!hs[k]->initialised) return LBM3D_E_STATE;
+        if (hs[k]->mode != hs[0]->mode) return LBM3D_E_INVAL;
+        if (!tiled_fits(hs[k]->mode, hs[k]->g)) return LBM3D_E_INVAL;
+    }
+    if (launches <= 0) launches = 5;
+    hipStream_t s = hs[0]->stream;
+    for (int32_t k = 0; k < count; k++)
+        if (hipStreamSynchronize(hs[k]->stream) != hipSuccess) return LBM3D_E_DEVICE;
+    std::vector<lbm3d_solver*> members(hs, hs + count);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best_tz = 0;
+    float best_ms = -1.0f;
+    const int tzs[3] = {8, 16, 32};
+    for (int t : tzs) {
+        if (e != hipSuccess) break;
+        BatchPlan plan;
+        int32_t rc = plan.build(members, s, t);
+        if (rc) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc;
+        }
+        // parity 0 every time: each launch recomputes the same next level
+        for (int w = 0; w < 2 && e == hipSuccess; w++) e = plan.launch_once(s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int k = 0; k < launches && e == hipSuccess; k++) e = plan.launch_once(s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
+            best_ms = ms;
+            best_tz = t;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return herr2(e);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_batch_tz[hs[0]->mode] = best_tz;
+    }
+    if (tz) *tz = best_tz;
+    return LBM3D_OK;
+}

@@ -72,6 +72,8 @@ def _load():
         "lbm3d_step_timed": (I32, [P, I64, D]),
         "lbm3d_step_profiled": (I32, [P, I64, D, D]),
         "lbm3d_set_tile": (I32, [P, I32, I32]),
+        "lbm3d_tune": (I32, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "lbm3d_batch_tune": (I32, [ctypes.POINTER(P), I32, I32, ctypes.POINTER(I32)]),
         "lbm3d_get_tile": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "lbm3d_sync": (I32, [P]),
         "lbm3d_moments": (I32, [P, D, D, D, D, D]),
@@ -212,6 +214,13 @@ def lbm3d_get_tile(h):
     return by.value, tz.value
 
 
+def lbm3d_tune(h, launches: int = 10):
+    by = ctypes.c_int32(0)
+    tz = ctypes.c_int32(0)
+    _check(_lib.lbm3d_tune(h, int(launches), ctypes.byref(by), ctypes.byref(tz)), "lbm3d_tune")
+    return by.value, tz.value
+
+
 def lbm3d_sync(h):
     _check(_lib.lbm3d_sync(h), "lbm3d_sync")
 
@@ -253,6 +262,13 @@ def lbm3d_batch_step(handles, nsteps):
     arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
     ns = (ctypes.c_int64 * len(handles))(*[int(n) for n in nsteps])
     _check(_lib.lbm3d_batch_step(arr, len(handles), ns), "lbm3d_batch_step")
+
+
+def lbm3d_batch_tune(handles, launches: int = 5) -> int:
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    tz = ctypes.c_int32(0)
+    _check(_lib.lbm3d_batch_tune(arr, len(handles), int(launches), ctypes.byref(tz)), "lbm3d_batch_tune")
+    return tz.value
 
 
 def lbm3d_server_create(hbm_budget_bytes: int, max_active: int):
@@ -348,6 +364,9 @@ class Solver:
 
     def get_tile(self):
         return lbm3d_get_tile(self.h)
+
+    def tune(self, launches: int = 10):
+        return lbm3d_tune(self.h, launches)
 
     def moments(self, allow_nonfinite: bool = False):
         return lbm3d_moments(self.h, self.shape, allow_nonfinite)

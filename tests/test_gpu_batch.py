@@ -74,3 +74,23 @@ def test_batch_rejects_bad_arguments():
     assert ei.value.code == lbm3d.E_STATE
     lbm3d.lbm3d_batch_step([a.h], [0])
     assert a.status()[1] == 0
+
+
+def test_batch_autotuner_keeps_states():
+    lbm3d = _lib()
+    cases = _mix("fp32_t64")
+    solvers = []
+    for c in cases:
+        s = lbm3d.Solver(dict(c.params))
+        s.init(*c.fields)
+        s.step(3)
+        solvers.append(s)
+    before = [s.get_f() for s in solvers]
+    tz = lbm3d.lbm3d_batch_tune([s.h for s in solvers], 3)
+    assert tz in (8, 16, 32)
+    for s, f in zip(solvers, before):
+        assert np.array_equal(s.get_f(), f) and s.status()[1] == 3
+    lbm3d.lbm3d_batch_step([s.h for s in solvers], [9] * len(solvers))
+    for c, s in zip(cases, solvers):
+        assert np.array_equal(s.get_f(), _alone(c, 12)), c.name
+        s.close()

@@ -280,3 +280,24 @@ def test_switching_launch_shape_mid_run():
     b.set_tile(0, 1)
     b.step(10)
     assert np.array_equal(a.get_f(), b.get_f())
+
+
+def test_autotuner_keeps_state_and_is_remembered():
+    """The tuner times launch shapes without changing the solve; the shape it
+    keeps gives bitwise the same run, and a new solve of the same shape
+    starts with it."""
+    lbm3d = _lib()
+    case = inputs.shock_bubble(18, grid=(128, 40, 24), precision="fp32_t64", mach=3.0, ratio=2.0)
+    a, _ = gpu_run(case, 5)
+    f5 = a.get_f()
+    by, tz = a.tune(4)
+    assert a.get_tile() == (by, tz)
+    assert a.status()[1] == 5
+    assert np.array_equal(a.get_f(), f5)
+    a.step(12)
+    b = lbm3d.Solver(dict(case.params))
+    assert b.get_tile() == (by, tz)
+    b.set_tile(0, 1)
+    b.init(*case.fields)
+    b.step(17)
+    assert np.array_equal(a.get_f(), b.get_f())
