@@ -127,11 +127,17 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
         nlblocks_ += (int)((lines + 63) / 64);
     }
     nljobs_ = (int)ljobs.size();
+    std::vector<int32_t> block_job((size_t)nlblocks_);
+    for (int j = 0; j < nljobs_; j++) {
+        const int end = j + 1 < nljobs_ ? ljobs[j + 1].first : nlblocks_;
+        for (int b = ljobs[j].first; b < end; b++) block_job[(size_t)b] = j;
+    }
 
     const size_t sb = table.size() * sizeof(BatchSolve);
     const size_t tb = (size_t)n * sizeof(BatchTile);
     const size_t lb = ljobs.size() * sizeof(BatchLayerJob);
-    const size_t need = ((sb + 255) / 256) * 256 + ((tb + 255) / 256) * 256 + lb + 256;
+    const size_t bb = block_job.size() * sizeof(int32_t);
+    const size_t need = ((sb + 255) / 256) * 256 + ((tb + 255) / 256) * 256 + ((lb + 255) / 256) * 256 + bb + 256;
     if (need > dbytes_) {
         if (dmem_) (void)hipFree(dmem_);
         dmem_ = nullptr;
@@ -143,9 +149,11 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     dsolves_ = (BatchSolve*)dmem_;
     dtiles_ = (BatchTile*)((char*)dmem_ + ((sb + 255) / 256) * 256);
     dlayers_ = (BatchLayerJob*)((char*)dtiles_ + ((tb + 255) / 256) * 256);
+    dblockjob_ = (int32_t*)((char*)dlayers_ + ((lb + 255) / 256) * 256);
     hipError_t e = hipMemcpyAsync(dsolves_, table.data(), sb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dtiles_, tiles.data(), tb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && lb) e = hipMemcpyAsync(dlayers_, ljobs.data(), lb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && bb) e = hipMemcpyAsync(dblockjob_, block_job.data(), bb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables die at return
     return herr(e);
 }
@@ -157,7 +165,7 @@ hipError_t BatchPlan::enqueue(int parity, hipStream_t s)
     hipError_t e = launch_batch_step(mode_, by_, dsolves_, dtiles_, ntiles_, nblocks_, parity, s);
     if (e != hipSuccess) return e;
     // boundary layers the tiles do not form themselves, all members at once
-    return launch_batch_layers(mode_, dsolves_, dlayers_, nljobs_, nlblocks_, parity, s);
+    return launch_batch_layers(mode_, dsolves_, dlayers_, dblockjob_, nlblocks_, parity, s);
 }
 
 int32_t BatchPlan::run(int64_t k, hipStream_t s)

@@ -42,6 +42,7 @@ private:
     BatchSolve* dsolves_ = nullptr;
     BatchTile* dtiles_ = nullptr;
     BatchLayerJob* dlayers_ = nullptr;  // boundary-layer jobs (sorted by first workgroup)
+    int32_t* dblockjob_ = nullptr;      // job of each boundary-layer workgroup
     int nljobs_ = 0, nlblocks_ = 0;
     std::vector<uint32_t> ghost_rest_;  // per member: faces left to the boundary-layer launch
     std::vector<int> cur0_;             // per member: current buffer at build()

@@ -237,21 +237,16 @@ k_layers(StepArgs<MODE> A, Model<double> md, Model<float> mf, FixedStates fx, ui
 }
 
 // Boundary layers of many solves in one launch: job k covers workgroups
-// [first[k], first[k+1]) of solve jobs[k].solve (faces jobs[k].faces), so
-// each workgroup finds its job by a binary search over the sorted table.
+// [first[k], first[k+1]) of solve jobs[k].solve (faces jobs[k].faces);
+// block_job[b] names the job of workgroup b.
 template <int MODE>
 __global__ void __launch_bounds__(64)
-k_layers_batch(const BatchSolve* __restrict__ solves, const BatchLayerJob* __restrict__ jobs, int njobs, int parity)
+k_layers_batch(const BatchSolve* __restrict__ solves, const BatchLayerJob* __restrict__ jobs,
+               const int32_t* __restrict__ block_job, int parity)
 {
     using S = typename Types<MODE>::S;
     const int b = (int)blockIdx.x;
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].first <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const BatchLayerJob jb = jobs[lo];
+    const BatchLayerJob jb = jobs[block_job[b]];
     const BatchSolve& d = solves[jb.solve];
     StepArgs<MODE> A;
     A.g = d.g;
@@ -442,7 +437,7 @@ uint32_t ghost_faces(const Grid& g, const FaceBC& bc, bool tiled)
         const int kind = bc.kind[face], axis = face >> 1;
         if (kind == BC_INFLOW) continue;
         if (tiled && LBM3D_X_IN_TILE && axis == 0 && g.nx % TILE_X == 0) continue;
-        if (tiled && LBM3D_WRAP_YZ && axis > 0 && kind == BC_PERIODIC) continue;
+        if (tiled && LBM3D_WRAP && kind == BC_PERIODIC) continue;
         m |= 1u << face;
     }
     return m;
@@ -577,11 +572,11 @@ hipError_t launch_pack(int mode, const Grid& g, const void* f, void* dense, bool
     return hipGetLastError();
 }
 
-hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLayerJob* jobs, int njobs, int nblocks,
-                               int parity, hipStream_t s)
+hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLayerJob* jobs, const int32_t* block_job,
+                               int nblocks, int parity, hipStream_t s)
 {
-    if (njobs <= 0 || nblocks <= 0) return hipSuccess;
-    LBM3D_DISPATCH(mode, k_layers_batch<MD><<<dim3(nblocks), dim3(64), 0, s>>>(solves, jobs, njobs, parity));
+    if (nblocks <= 0) return hipSuccess;
+    LBM3D_DISPATCH(mode, k_layers_batch<MD><<<dim3(nblocks), dim3(64), 0, s>>>(solves, jobs, block_job, parity));
     return hipGetLastError();
 }
 

@@ -91,8 +91,8 @@ bool tiled_fits(int mode, const Grid& g);
 // Faces whose boundary layers the boundary-layer kernel refreshes after
 // every step.  Fixed-state layers are written once at init.  The tiled
 // kernels form the x layers themselves when 64-wide tiles cover x exactly
-// (nx a multiple of 64) and wrap periodic y and z faces, so with `tiled`
-// those faces need no layers in memory.
+// (nx a multiple of 64) and wrap periodic faces, so with `tiled` those
+// faces need no layers in memory.
 uint32_t ghost_faces(const Grid& g, const FaceBC& bc, bool tiled);
 hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg& tc, const Model<double>& md,
                        const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
@@ -113,8 +113,8 @@ hipError_t launch_pack(int mode, const Grid& g, const void* f, void* dense, bool
 // One step of every solve in `solves` (device table) over the packed tile
 // list (device); `parity` selects f[cur0 ^ parity] as the current level.
 // Boundary layers of the members of a batch after a step (one launch).
-hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLayerJob* jobs, int njobs, int nblocks,
-                               int parity, hipStream_t s);
+hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLayerJob* jobs, const int32_t* block_job,
+                               int nblocks, int parity, hipStream_t s);
 hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles, int ntiles,
                              int nblocks, int parity, hipStream_t s);
 

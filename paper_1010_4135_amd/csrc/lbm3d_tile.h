@@ -35,16 +35,16 @@ namespace lbm3d {
 
 // Build-time tuning knobs: tiles are numbered with x fastest (1) or y
 // fastest (0) before the XCD grouping; the tiles form the x boundary layers
-// themselves (1) or read them from memory (0); periodic y / z faces wrap
-// (1) or are read from memory (0).
+// themselves (1) or read them from memory (0); periodic faces wrap (1) or
+// are read from memory (0).
 #ifndef LBM3D_TILE_ORDER_X
 #define LBM3D_TILE_ORDER_X 1
 #endif
 #ifndef LBM3D_X_IN_TILE
 #define LBM3D_X_IN_TILE 1
 #endif
-#ifndef LBM3D_WRAP_YZ
-#define LBM3D_WRAP_YZ 1
+#ifndef LBM3D_WRAP
+#define LBM3D_WRAP 1
 #endif
 
 // Workgroup barrier that orders LDS accesses only: global loads in flight
@@ -324,19 +324,25 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     //    extrapolated and reflecting columns are formed per plane from the
     //    moments of the nodes next to the face (Sec. 4 (2)), by the
     //    wavefront that owns the row;
-    //  - periodic y and z faces: rows and planes wrap.
+    //  - periodic faces: columns, rows and planes wrap (any nx).
     // Other layers are read from memory.  Every load is clamped into the
     // padded array: nodes beyond the last layer are never read by an
     // active node's stencil.
     const bool xin_tile = LBM3D_X_IN_TILE && (g.nx % TILE_X) == 0;
     const bool lf = xin_tile && x0 == 0, rf = xin_tile && x0 + TILE_X == g.nx;
     const int kL = A.bc.kind[0], kR = A.bc.kind[1];
-    const bool ywrap = LBM3D_WRAP_YZ && A.bc.kind[2] == BC_PERIODIC;
-    const bool zwrap = LBM3D_WRAP_YZ && A.bc.kind[4] == BC_PERIODIC;
+    const bool xwrap = LBM3D_WRAP && kL == BC_PERIODIC;
+    const bool ywrap = LBM3D_WRAP && A.bc.kind[2] == BC_PERIODIC;
+    const bool zwrap = LBM3D_WRAP && A.bc.kind[4] == BC_PERIODIC;
+    // x wrapped into [0, nx) for the columns a stencil can read (-2 .. nx+1);
+    // columns further right only feed lanes outside the grid
+    auto xw = [&](int v) {
+        return v < 0 ? ((v % g.nx) + g.nx) % g.nx : (v < g.nx ? v : (v < g.nx + 2 ? (v - g.nx) % g.nx : 0));
+    };
     auto zsel = [&](int zz) { return zwrap ? wrap_idx(zz, g.nz) : min(zz, zmax); };
     // the plane after zz (wrapped or clamped like zsel), without a division
     auto znext = [&](int zz) { return zwrap ? (zz + 1 == g.nz ? 0 : zz + 1) : min(zz + 1, zmax); };
-    const int xl = min(x, g.nx + 1);
+    const int xl = xwrap ? xw(x) : min(x, g.nx + 1);
     const int yl = ywrap ? wrap_idx(min(y, g.ny + 9), g.ny) : min(y, g.ny + 1);
     // uniform base of velocity i at plane zz (node (0, 0, zz))
     auto base = [&](const S* p, int i, int zz) { return p + ((int64_t)i * sv + g.org + (int64_t)zz * sz); };
@@ -378,15 +384,14 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     const int hv = min(tx >> 2, NV - 1), hp = tx & 3;
     int hx = hp == 0 ? x0 - 2 : hp == 1 ? x0 - 1 : hp == 2 ? x0 + TILE_X : x0 + TILE_X + 1;
     bool hlane = tx < 4 * NV;  // this lane's gathered value is staged
-    if (lf && hp < 2) {
-        if (kL == BC_PERIODIC) hx += g.nx;
-        else { hx = 0; hlane = false; }  // formed in the tile; load a cached column
+    if (xwrap) {
+        hx = xw(hx);
+    } else {
+        // columns formed in the tile: load a cached column instead
+        if (lf && hp < 2) { hx = 0; hlane = false; }
+        if (rf && hp >= 2) { hx = g.nx - 1; hlane = false; }
+        hx = min(hx, g.nx + 1);
     }
-    if (rf && hp >= 2) {
-        if (kR == BC_PERIODIC) hx -= g.nx;
-        else { hx = g.nx - 1; hlane = false; }
-    }
-    hx = min(hx, g.nx + 1);
     const S* hptr = f + ((int64_t)hv * sv + g.org + (int64_t)yl * sy + hx);
     const int hcol = hp < 2 ? hp : hp + TILE_X;
     constexpr int NJ = halo_jobs();

@@ -236,10 +236,12 @@ def _tile_cases(precision):
     c = inputs.smooth_periodic(16, grid=(128, 12, 9), amp=0.3, precision=precision)
     c.params = dict(c.params, bc=(0, 0, 3, 1, 1, 3))
     out.append(c)
+    # periodic in every axis with ragged x (70 = 64 + 6) and tiny y
+    out.append(inputs.smooth_periodic(19, grid=(70, 5, 11), amp=0.3, precision=precision))
     return out
 
 
-@pytest.mark.parametrize("which", range(4))
+@pytest.mark.parametrize("which", range(5))
 @pytest.mark.parametrize("precision", ["fp64", "fp32_t64"])
 def test_results_do_not_depend_on_tile_shape(precision, which):
     """Every launch shape (untiled, and 64 x BY x TZ tiles with ragged edges
