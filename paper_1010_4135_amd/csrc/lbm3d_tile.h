@@ -46,6 +46,11 @@ namespace lbm3d {
 #ifndef LBM3D_WRAP
 #define LBM3D_WRAP 1
 #endif
+// LBM3D_LOAD_INTERLEAVE: the loads of the planes ahead are issued one per
+// velocity between the updates (1) or together before the barrier (0).
+#ifndef LBM3D_LOAD_INTERLEAVE
+#define LBM3D_LOAD_INTERLEAVE 1
+#endif
 
 // Workgroup barrier that orders LDS accesses only: global loads in flight
 // (the prefetch of the planes ahead) and global stores are not drained.
@@ -495,18 +500,18 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
         constexpr int K = decltype(kc)::value;
         TilePlane<BY, S>& cur = P[K & 1];
         TilePlane<BY, S>& nxt = P[(K + 1) & 1];
-        {
-            // planes z+2 (v_z >= 0) and z+3 (v_z < 0), walked velocity by velocity
-            const S* pa = base(f, 0, za);
-            const int64_t db = (int64_t)(zb - za) * sz;
-            static_for<NV>([&](auto ic) {
-                constexpr int I = decltype(ic)::value;
-                pa = sreg(pa);
-                const S* p = vsign(I, 2) < 0 ? sreg(pa + db) : pa;
-                q[I][(K + 3) & 3] = static_cast<C>(ld_at(p, colb));
-                pa += sv;
-            });
-        }
+        // planes z+2 (v_z >= 0) and z+3 (v_z < 0), walked velocity by velocity;
+        // the slot they fill is not read in this plane
+        const S* pa = base(f, 0, za);
+        const int64_t db = (int64_t)(zb - za) * sz;
+        auto ring_load = [&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            pa = sreg(pa);
+            const S* p = vsign(I, 2) < 0 ? sreg(pa + db) : pa;
+            q[I][(K + 3) & 3] = static_cast<C>(ld_at(p, colb));
+            pa += sv;
+        };
+        if constexpr (!LBM3D_LOAD_INTERLEAVE) static_for<NV>(ring_load);
         load_halo(K & 1, za);
         za = znext(za);
         zb = znext(zb);
@@ -579,6 +584,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
             po = sreg(po);
             st_at(po, outb, static_cast<S>(out));
             po += sv;
+            if constexpr (LBM3D_LOAD_INTERLEAVE) ring_load(ic);
         });
 
         // stage plane z+1: own values and its halo
