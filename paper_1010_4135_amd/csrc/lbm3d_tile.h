@@ -51,6 +51,13 @@ namespace lbm3d {
 #ifndef LBM3D_LOAD_INTERLEAVE
 #define LBM3D_LOAD_INTERLEAVE 1
 #endif
+// LBM3D_VCONST: FP64 model constants of the moments and the equilibrium
+// kept in vector registers by the 8-row tiles of the FP32_T64 mode (1: the
+// equilibrium coefficients, 2: those and the moment constants, 0: none,
+// left to the scalar registers).
+#ifndef LBM3D_VCONST
+#define LBM3D_VCONST 2
+#endif
 
 // Workgroup barrier that orders LDS accesses only: global loads in flight
 // (the prefetch of the planes ahead) and global stores are not drained.
@@ -117,38 +124,45 @@ struct StepArgs {
 
 // Extrapolated boundary states of Sec. 4 (2): layer 1 = 2 q(i0) - q(i1),
 // layer 2 = 2 (layer 1) - q(i0).
+// State of boundary layer j (1: the layer next to the face, 2: the one
+// beyond it) from the moments of the node next to the face (a) and of the
+// node after that (b), Sec. 4 (2):
+//  - extrapolating face: (rho, u, T) extrapolated linearly through b and
+//    a, i.e. a + j (a - b);
+//  - reflecting face: a with the normal velocity set to zero (layer 1, the
+//    wall) or negated (layer 2, the mirror image).
+// Both are one formula, q = a + c (a - b) with the normal velocity then
+// scaled by m: (c, m) = (j, 1) when extrapolating, (0, 0) or (0, -1) when
+// reflecting (c = 0 gives q = a exactly, whatever b).  A per-lane (c, m)
+// then forms any layer without selecting between the two rules.
 template <typename M>
-__device__ __forceinline__ void extrapolate(const Macro<M>& a, const Macro<M>& b, Macro<M>& l1, Macro<M>& l2)
+__device__ __forceinline__ void layer_coefs(int kind, int j, M& c, M& m)
 {
-    l1.rho = M(2) * a.rho - b.rho;
-    l1.ux = M(2) * a.ux - b.ux;
-    l1.uy = M(2) * a.uy - b.uy;
-    l1.uz = M(2) * a.uz - b.uz;
-    l1.T = M(2) * a.T - b.T;
-    l2.rho = M(2) * l1.rho - a.rho;
-    l2.ux = M(2) * l1.ux - a.ux;
-    l2.uy = M(2) * l1.uy - a.uy;
-    l2.uz = M(2) * l1.uz - a.uz;
-    l2.T = M(2) * l1.T - a.T;
+    const bool refl = kind == BC_REFLECT;
+    const int ci = refl ? 0 : j;
+    const int mi = refl ? 1 - j : 1;
+    c = static_cast<M>(ci);
+    m = static_cast<M>(mi);
 }
 
-// Reflecting wall (Sec. 4 (2)): wall layer = q with zero normal velocity,
-// mirror layer = q with the normal velocity negated.
 template <typename M>
-__device__ __forceinline__ void reflect(const Macro<M>& a, int axis, Macro<M>& wall, Macro<M>& mirror)
+__device__ __forceinline__ Macro<M> layer_state(const Macro<M>& a, const Macro<M>& b, M c, M m, int axis)
 {
-    wall = a;
-    mirror = a;
-    if (axis == 0) {
-        wall.ux = M(0);
-        mirror.ux = -a.ux;
-    } else if (axis == 1) {
-        wall.uy = M(0);
-        mirror.uy = -a.uy;
-    } else {
-        wall.uz = M(0);
-        mirror.uz = -a.uz;
-    }
+    const M drho = a.rho - b.rho;
+    const M dux = a.ux - b.ux;
+    const M duy = a.uy - b.uy;
+    const M duz = a.uz - b.uz;
+    const M dT = a.T - b.T;
+    Macro<M> q;
+    q.rho = fmac(c, drho, a.rho);
+    q.ux = fmac(c, dux, a.ux);
+    q.uy = fmac(c, duy, a.uy);
+    q.uz = fmac(c, duz, a.uz);
+    q.T = fmac(c, dT, a.T);
+    if (axis == 0) q.ux = m * q.ux;
+    if (axis == 1) q.uy = m * q.uy;
+    if (axis == 2) q.uz = m * q.uz;
+    return q;
 }
 
 template <typename S, typename C>
@@ -191,15 +205,17 @@ __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<
 #pragma unroll
     for (int i = 0; i < NV; i++) a[i] = static_cast<C>((fn + i * sv)[at(i0)]);
     const Macro<M> q0 = moments<M, C>(a, mm);
-    Macro<M> l1, l2;
-    if (kind == BC_REFLECT) {
-        reflect(q0, axis, l1, l2);
-    } else {  // BC_OUTFLOW
+    Macro<M> q1 = q0;  // (unused by a reflecting face)
+    if (kind == BC_OUTFLOW) {
 #pragma unroll
         for (int i = 0; i < NV; i++) a[i] = static_cast<C>((fn + i * sv)[at(i1)]);
-        const Macro<M> q1 = moments<M, C>(a, mm);
-        extrapolate(q0, q1, l1, l2);
+        q1 = moments<M, C>(a, mm);
     }
+    M c1, m1, c2, m2;
+    layer_coefs(kind, 1, c1, m1);
+    layer_coefs(kind, 2, c2, m2);
+    const Macro<M> l1 = layer_state(q0, q1, c1, m1, axis);
+    const Macro<M> l2 = layer_state(q0, q1, c2, m2, axis);
     equilibrium<C, M>(l1, mm, mc, a);
     store_node(fn, sv, at(g1), a);
     equilibrium<C, M>(l2, mm, mc, a);
@@ -287,17 +303,6 @@ __device__ __forceinline__ Macro<M> shfl_macro(const Macro<M>& q, int l)
     r.T = lane_get(q.T, l);
     return r;
 }
-template <typename M>
-__device__ __forceinline__ Macro<M> pick_macro(bool b, const Macro<M>& x, const Macro<M>& y)
-{
-    Macro<M> r;
-    r.rho = b ? x.rho : y.rho;
-    r.ux = b ? x.ux : y.ux;
-    r.uy = b ? x.uy : y.uy;
-    r.uz = b ? x.uz : y.uz;
-    r.T = b ? x.T : y.T;
-    return r;
-}
 
 // XF: this tile forms extrapolating or reflecting x layers itself (see
 // x_forms(); the caller selects the instantiation per tile).
@@ -311,7 +316,23 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     using M = typename Types<MODE>::M;
     constexpr uint32_t ES = sizeof(S);
     const Model<C>& mc = pick<C>(md, mf);
-    const Model<M>& mm = pick<M>(md, mf);
+    Model<M> mm = pick<M>(md, mf);
+    if constexpr (MODE == MODE_FP32_T64 && BY >= 8 && LBM3D_VCONST > 0) {
+        // Uniform FP64 constants held in vector registers.  The scalar
+        // file cannot hold them beside the pointers and loop state, and the
+        // compiler would spill them into vector lanes and read them back
+        // (one VALU instruction per dword) in every plane.  The 8-row
+        // tiles have the vector registers to spare at two wavefronts per
+        // SIMD; the smaller tiles do not, and FP32 constants fit the
+        // scalar file.
+        auto vk = [](M& v) { asm volatile("" : "+v"(v)); };
+        vk(mm.r_aT);
+        vk(mm.x_a0); vk(mm.x_aT); vk(mm.x_au); vk(mm.x_b0); vk(mm.x_bT); vk(mm.x_bu);
+        vk(mm.d_a0); vk(mm.d_aT); vk(mm.d_au); vk(mm.d_b0); vk(mm.d_bT); vk(mm.d_bu);
+        if constexpr (LBM3D_VCONST > 1) {
+            vk(mm.c1); vk(mm.k); vk(mm.e0sq); vk(mm.c1sq); vk(mm.c2sq); vk(mm.inv_b);
+        }
+    }
     const Grid& g = A.g;
     const S* __restrict__ f = A.f;
     S* __restrict__ fn = A.fn;
@@ -474,11 +495,9 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
         const bool on = ll < 2 * NV && (side ? rf : lf) && (kind == BC_OUTFLOW || kind == BC_REFLECT);
         const Macro<M> q0 = shfl_macro(mq, side ? TILE_X - 1 : 0);
         const Macro<M> q1 = shfl_macro(mq, side ? TILE_X - 2 : 1);
-        Macro<M> r1, r2, e1, e2;
-        reflect(q0, 0, r1, r2);
-        extrapolate(q0, q1, e1, e2);
-        const bool refl = kind == BC_REFLECT;
-        const Macro<M> qs = pick_macro(j == 0, pick_macro(refl, r1, e1), pick_macro(refl, r2, e2));
+        M c, m;
+        layer_coefs(kind, j + 1, c, m);
+        const Macro<M> qs = layer_state(q0, q1, c, m, 0);
         const C val = feq_vel<C>(iv, eq_coef<C, M>(qs, mm), mc);
         if (on) T.v[iv][ty + 2][side ? TILE_X + 2 + j : 1 - j] = static_cast<S>(val);
     };
