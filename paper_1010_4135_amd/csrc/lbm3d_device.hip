@@ -93,6 +93,11 @@ k_step(Grid g, Model<double> md, Model<float> mf, const typename Types<MODE>::S*
 #else
 #define LBM3D_TILED_ATTR
 #endif
+// LBM3D_BATCH_VK: the batched step's tiles hold the FP64 model constants in
+// vector registers too (1) or leave them to the scalar file (0).
+#ifndef LBM3D_BATCH_VK
+#define LBM3D_BATCH_VK 1
+#endif
 
 template <int MODE, int BY>
 __global__ void __launch_bounds__(TILE_X * BY) LBM3D_TILED_ATTR
@@ -138,7 +143,7 @@ k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict_
         A.health = d.health;
 #pragma unroll
         for (int k = 0; k < 10; k++) A.xin[k / 5][k % 5] = d.xin[k / 5][k % 5];
-        step_tile<MODE, BY>(A, d.md, d.mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
+        step_tile<MODE, BY, LBM3D_BATCH_VK>(A, d.md, d.mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
         lds_barrier();  // the plane buffers are reused by the next tile
     }
 }
@@ -527,7 +532,7 @@ hipError_t launch_ghosts(int mode, const Grid& g, const FaceBC& bc, const Model<
         StepArgs<MD> A{};
         A.g = g;
         A.bc = bc;
-            A.f = nullptr;
+        A.f = nullptr;
         A.fn = (typename Types<MD>::S*)f;
         A.health = nullptr;
         k_layers<MD><<<dim3(nb), dim3(64), 0, s>>>(A, md, mf, fx, faces);

@@ -122,8 +122,6 @@ struct StepArgs {
     double xin[2][5];  // fixed states of the x faces (rho, ux, uy, uz, T)
 };
 
-// Extrapolated boundary states of Sec. 4 (2): layer 1 = 2 q(i0) - q(i1),
-// layer 2 = 2 (layer 1) - q(i0).
 // State of boundary layer j (1: the layer next to the face, 2: the one
 // beyond it) from the moments of the node next to the face (a) and of the
 // node after that (b), Sec. 4 (2):
@@ -172,6 +170,19 @@ __device__ __forceinline__ void store_node(S* __restrict__ fn, int64_t sv, uint3
     for (int i = 0; i < NV; i++) (fn + i * sv)[off] = static_cast<S>(v[i]);
 }
 
+// Layer node of a face: the first layer is read by every velocity's
+// stencil, the second only by the velocities advected into the grid through
+// that face (sign `in` along the axis), whose NND flux reaches two nodes
+// upwind.  Only those values are written.
+template <typename S, typename C>
+__device__ __forceinline__ void store_layer(S* __restrict__ fn, int64_t sv, uint32_t off, const C (&v)[NV],
+                                            bool second, int axis, int in)
+{
+#pragma unroll
+    for (int i = 0; i < NV; i++)
+        if (!second || vsign(i, axis) == in) (fn + i * sv)[off] = static_cast<S>(v[i]);
+}
+
 // Boundary layers of one face on the line of nodes through `line` (offset
 // of the line's node 0, node stride st along the face normal, n nodes):
 // periodic copy, reflecting wall or linear extrapolation, the layer f being
@@ -188,6 +199,7 @@ __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<
     S* __restrict__ fn = A.fn;
     const int side = face & 1, kind = A.bc.kind[face], axis = face >> 1;
     const int g1 = side ? n : -1, g2 = side ? n + 1 : -2;  // wall / first layer, second layer
+    const int in = side ? -1 : 1;
     auto at = [&](int c) { return line + (uint32_t)c * st; };
     C a[NV];
     if (kind == BC_PERIODIC) {
@@ -196,8 +208,9 @@ __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<
         for (int k = 0; k < 2; k++) {
             const int src = ((gs[k] % n) + n) % n;
 #pragma unroll
-            for (int i = 0; i < NV; i++) a[i] = static_cast<C>((fn + i * sv)[at(src)]);
-            store_node(fn, sv, at(gs[k]), a);
+            for (int i = 0; i < NV; i++)
+                if (k == 0 || vsign(i, axis) == in) a[i] = static_cast<C>((fn + i * sv)[at(src)]);
+            store_layer(fn, sv, at(gs[k]), a, k == 1, axis, in);
         }
         return;
     }
@@ -217,9 +230,9 @@ __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<
     const Macro<M> l1 = layer_state(q0, q1, c1, m1, axis);
     const Macro<M> l2 = layer_state(q0, q1, c2, m2, axis);
     equilibrium<C, M>(l1, mm, mc, a);
-    store_node(fn, sv, at(g1), a);
+    store_layer(fn, sv, at(g1), a, false, axis, in);
     equilibrium<C, M>(l2, mm, mc, a);
-    store_node(fn, sv, at(g2), a);
+    store_layer(fn, sv, at(g2), a, true, axis, in);
 }
 
 // Ring slot of plane z + j of velocity I's column at unroll phase K: the
@@ -305,8 +318,9 @@ __device__ __forceinline__ Macro<M> shfl_macro(const Macro<M>& q, int l)
 }
 
 // XF: this tile forms extrapolating or reflecting x layers itself (see
-// x_forms(); the caller selects the instantiation per tile).
-template <int MODE, int BY, bool XF>
+// x_forms(); the caller selects the instantiation per tile).  VK: the FP64
+// model constants may be held in vector registers (see below).
+template <int MODE, int BY, bool XF, bool VK>
 __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model<double>& md,
                                             const Model<float>& mf, int x0, int y0, int z0, int z1,
                                             TilePlane<BY, typename Types<MODE>::S> (&P)[2])
@@ -317,7 +331,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     constexpr uint32_t ES = sizeof(S);
     const Model<C>& mc = pick<C>(md, mf);
     Model<M> mm = pick<M>(md, mf);
-    if constexpr (MODE == MODE_FP32_T64 && BY >= 8 && LBM3D_VCONST > 0) {
+    if constexpr (VK && MODE == MODE_FP32_T64 && BY >= 8 && LBM3D_VCONST > 0) {
         // Uniform FP64 constants held in vector registers.  The scalar
         // file cannot hold them beside the pointers and loop state, and the
         // compiler would spill them into vector lanes and read them back
@@ -636,15 +650,15 @@ __device__ __forceinline__ bool x_forms(const StepArgs<MODE>& A, int x0)
     return (x0 == 0 && formed(A.bc.kind[0])) || (x0 + TILE_X == A.g.nx && formed(A.bc.kind[1]));
 }
 
-template <int MODE, int BY>
+template <int MODE, int BY, bool VK = true>
 __device__ __forceinline__ void step_tile(const StepArgs<MODE>& A, const Model<double>& md,
                                           const Model<float>& mf, int x0, int y0, int z0, int z1,
                                           TilePlane<BY, typename Types<MODE>::S> (&P)[2])
 {
     if (x_forms(A, x0))
-        step_tile_x<MODE, BY, true>(A, md, mf, x0, y0, z0, z1, P);
+        step_tile_x<MODE, BY, true, VK>(A, md, mf, x0, y0, z0, z1, P);
     else
-        step_tile_x<MODE, BY, false>(A, md, mf, x0, y0, z0, z1, P);
+        step_tile_x<MODE, BY, false, VK>(A, md, mf, x0, y0, z0, z1, P);
 }
 
 // Tile order: tiles are numbered with x (or y) fastest, then the other
