@@ -129,29 +129,37 @@ Grid make_grid(const lbm3d_params* p)
     g.nx = p->nx;
     g.ny = p->ny;
     g.nz = p->nz;
-    const int64_t ox = line;
+    const bool dense = dense_rows(p->nx);
+    // dense rows: the interior only, rows start on a line (nx is a multiple
+    // of 64 elements); otherwise the x layers pad the rows
+    const int64_t ox = dense ? 0 : line;
 #if LBM3D_SHARED_GHOST_LINE
     // one cache line of padding per row, holding the two right layer nodes
     // of the row (its first elements) and the two left layer nodes of the
     // next row (its last elements); interior rows start on a line
-    const int64_t mx = (p->nx + line - 1) / line * line + line;
+    const int64_t mxp = (p->nx + line - 1) / line * line + line;
 #else
-    const int64_t mx = ((ox + p->nx + NG) + line - 1) / line * line;
+    const int64_t mxp = ((ox + p->nx + NG) + line - 1) / line * line;
 #endif
+    const int64_t mx = dense ? p->nx : mxp;
     const int64_t my = p->ny + 2 * NG;
     const int64_t mz = p->nz + 2 * NG;
+    g.my = (int32_t)my;
     g.sy = mx;
     g.sz = mx * my;
+    // one spare line past the array: the sink of the step kernel's stores
+    // from lanes outside the grid (the right layer nodes of the last row of
+    // a padded array reach two elements past sz * mz)
+    g.sink = g.sz * mz + line;
+    // dense rows: the x layers of every row (4 nodes) after the sink line
+    g.xg = dense ? g.sz * mz + 2 * line : 0;
+    const int64_t end = dense ? g.xg + 4 * my * mz : g.sz * mz + 2 * line;
     // velocity planes are separated by an odd number of 256-byte blocks so
     // that the 15 streams do not start on the same memory channel
     const int64_t blk = 256 / (int64_t)elem_size(p->precision);
-    // one spare element past the plane: the sink of the step kernel's
-    // stores from lanes outside the grid
-    // (the right layer nodes of the last row reach two elements past sz * mz)
-    int64_t sv = (g.sz * mz + 2 * line + blk - 1) / blk;
+    int64_t sv = (end + blk - 1) / blk;
     if ((sv & 1) == 0) sv += 1;
     g.sv = sv * blk;
-    g.sink = g.sz * mz + line;
     g.org = NG * g.sz + NG * g.sy + ox;
     return g;
 }

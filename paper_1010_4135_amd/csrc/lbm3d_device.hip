@@ -17,42 +17,63 @@ namespace lbm3d {
 // operations per node (node_update and the NND helpers), so they agree
 // bitwise.
 template <int I, typename S, typename C>
-__device__ __forceinline__ void update_one(const S* __restrict__ fi, S* __restrict__ fo,
-                                           int64_t sy, int64_t sz, C f0, C feq,
+__device__ __forceinline__ void update_one(const S* __restrict__ fi, S* __restrict__ fo, int64_t site,
+                                           const int64_t (&xo)[4], int64_t sy, int64_t sz, C f0, C feq,
                                            const Model<C>& m)
 {
     constexpr int SG[3] = {vsign(I, 0), vsign(I, 1), vsign(I, 2)};
     constexpr int G = vgroup(I);
-    const int64_t st[3] = {1, sy, sz};
+    // neighbour at distance d (-2, -1, 1, 2) along axis a: x neighbours
+    // through the per-thread offsets xo (which reach the x layers), y and z
+    // neighbours by stride
+    auto nb = [&](int a, int d) {
+        const int64_t o = a == 0 ? xo[d < 0 ? d + 2 : d + 1] : site + d * (a == 1 ? sy : sz);
+        return static_cast<C>(fi[o]);
+    };
     C D[3] = {C(0), C(0), C(0)}, L[3] = {C(0), C(0), C(0)};
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        const int64_t s = st[a];
         if (SG[a] > 0) {
-            const C fm2 = static_cast<C>(fi[-2 * s]), fm1 = static_cast<C>(fi[-s]), fp1 = static_cast<C>(fi[s]);
+            const C fm2 = nb(a, -2), fm1 = nb(a, -1), fp1 = nb(a, 1);
             const C e0 = f0 - fm1, e1 = fp1 - f0;
             D[a] = nnd_pos(fm1 - fm2, e0, e1);
             L[a] = e1 - e0;
         } else if (SG[a] < 0) {
-            const C fm1 = static_cast<C>(fi[-s]), fp1 = static_cast<C>(fi[s]), fp2 = static_cast<C>(fi[2 * s]);
+            const C fm1 = nb(a, -1), fp1 = nb(a, 1), fp2 = nb(a, 2);
             const C e0 = f0 - fm1, e1 = fp1 - f0;
             D[a] = nnd_neg(e0, e1, fp2 - fp1);
             L[a] = e1 - e0;
         } else if (G <= 1) {
-            L[a] = static_cast<C>(fi[-s]) + static_cast<C>(fi[s]);
+            L[a] = nb(a, -1) + nb(a, 1);
         }
     }
-    *fo = static_cast<S>(node_update<I, C>(f0, feq, D[0], D[1], D[2], L[0], L[1], L[2], m));
+    fo[site] = static_cast<S>(node_update<I, C>(f0, feq, D[0], D[1], D[2], L[0], L[1], L[2], m));
 }
 
 template <typename S, typename C, int I = 0>
 __device__ __forceinline__ void update_all(const S* __restrict__ f, S* __restrict__ fn, int64_t site,
-                                           int64_t sv, int64_t sy, int64_t sz, const C (&fc)[NV],
-                                           const C (&feq)[NV], const Model<C>& m)
+                                           const int64_t (&xo)[4], int64_t sv, int64_t sy, int64_t sz,
+                                           const C (&fc)[NV], const C (&feq)[NV], const Model<C>& m)
 {
     if constexpr (I < NV) {
-        update_one<I, S, C>(f + I * sv + site, fn + I * sv + site, sy, sz, fc[I], feq[I], m);
-        update_all<S, C, I + 1>(f, fn, site, sv, sy, sz, fc, feq, m);
+        update_one<I, S, C>(f + I * sv, fn + I * sv, site, xo, sy, sz, fc[I], feq[I], m);
+        update_all<S, C, I + 1>(f, fn, site, xo, sv, sy, sz, fc, feq, m);
+    }
+}
+
+// Offsets (within a velocity plane) of the x neighbours at distance -2, -1,
+// +1, +2 of node (x, y, z) at `site`: along the row, or in the x-layer block
+// for those beyond a face when rows are dense.
+__device__ __forceinline__ void x_offsets(const Grid& g, int x, int y, int z, int64_t site, int64_t (&xo)[4])
+{
+    const int d[4] = {-2, -1, 1, 2};
+    const int64_t row = g.xg + ((int64_t)(z + NG) * g.my + (y + NG)) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int xx = x + d[k];
+        const bool out = g.xg != 0 && (xx < 0 || xx >= g.nx);
+        const int64_t layer = xx < 0 ? xx + 2 : 2 + (xx - g.nx);  // 0: -2, 1: -1, 2: nx, 3: nx+1
+        xo[k] = out ? row + layer : site + d[k];
     }
 }
 
@@ -79,7 +100,9 @@ k_step(Grid g, Model<double> md, Model<float> mf, const typename Types<MODE>::S*
     if (hb) atomicOr(health, hb);
     C feq[NV];
     equilibrium<C, M>(q, mm, mc, feq);
-    update_all<S, C>(f, fn, site, g.sv, g.sy, g.sz, fc, feq, mc);
+    int64_t xo[4];
+    x_offsets(g, x, y, z, site, xo);
+    update_all<S, C>(f, fn, site, xo, g.sv, g.sy, g.sz, fc, feq, mc);
 }
 
 // Tiled fused step: one workgroup per 64 x BY x TZ tile (see lbm3d_tile.h).
@@ -214,6 +237,16 @@ __device__ __forceinline__ void layer_job(const StepArgs<MODE>& A, const Model<d
         const uint32_t line = (uint32_t)(g.org + (int64_t)cz * g.sz + (int64_t)cy * g.sy + cx);
         const uint32_t st = axis == 0 ? 1u : axis == 1 ? (uint32_t)g.sy : (uint32_t)g.sz;
         const int n = axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz;
+        const int side = face & 1;
+        // the two layer nodes of the line: beyond its ends, or in the
+        // x-layer block of a dense-row array
+        uint32_t l1 = line + (uint32_t)(side ? n : -1) * st;
+        uint32_t l2 = line + (uint32_t)(side ? n + 1 : -2) * st;
+        if (axis == 0 && g.xg != 0) {
+            const uint32_t row = (uint32_t)(g.xg + ((int64_t)(cz + NG) * g.my + (cy + NG)) * 4);
+            l1 = row + (side ? 2u : 1u);
+            l2 = row + (side ? 3u : 0u);
+        }
         if (A.bc.kind[face] == BC_INFLOW) {
             if (!fx) return;
             Macro<M> q;
@@ -224,11 +257,10 @@ __device__ __forceinline__ void layer_job(const StepArgs<MODE>& A, const Model<d
             q.T = static_cast<M>(fx->q[face][4]);
             C e[NV];
             equilibrium<C, M>(q, pick<M>(md, mf), pick<C>(md, mf), e);
-            const int side = face & 1;
-            store_node(A.fn, g.sv, line + (uint32_t)(side ? n : -1) * st, e);
-            store_node(A.fn, g.sv, line + (uint32_t)(side ? n + 1 : -2) * st, e);
+            store_node(A.fn, g.sv, l1, e);
+            store_node(A.fn, g.sv, l2, e);
         } else {
-            layer_line<MODE>(A, pick<M>(md, mf), pick<C>(md, mf), face, line, st, n);
+            layer_line<MODE>(A, pick<M>(md, mf), pick<C>(md, mf), face, line, st, n, l1, l2);
         }
         return;
     }

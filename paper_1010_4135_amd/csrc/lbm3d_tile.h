@@ -33,18 +33,10 @@
 
 namespace lbm3d {
 
-// Build-time tuning knobs: tiles are numbered with x fastest (1) or y
-// fastest (0) before the XCD grouping; the tiles form the x boundary layers
-// themselves (1) or read them from memory (0); periodic faces wrap (1) or
-// are read from memory (0).
+// Build-time tuning knob: tiles are numbered with x fastest (1) or y
+// fastest (0) before the XCD grouping.
 #ifndef LBM3D_TILE_ORDER_X
 #define LBM3D_TILE_ORDER_X 1
-#endif
-#ifndef LBM3D_X_IN_TILE
-#define LBM3D_X_IN_TILE 1
-#endif
-#ifndef LBM3D_WRAP
-#define LBM3D_WRAP 1
 #endif
 // LBM3D_LOAD_INTERLEAVE: the loads of the planes ahead are issued one per
 // velocity between the updates (1) or together before the barrier (0).
@@ -184,13 +176,14 @@ __device__ __forceinline__ void store_layer(S* __restrict__ fn, int64_t sv, uint
 }
 
 // Boundary layers of one face on the line of nodes through `line` (offset
-// of the line's node 0, node stride st along the face normal, n nodes):
+// of the line's node 0, node stride st along the face normal, n nodes; the
+// layer nodes next to the face and beyond it at offsets l1 and l2):
 // periodic copy, reflecting wall or linear extrapolation, the layer f being
 // the equilibrium of the layer state.
 template <int MODE>
 __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<typename Types<MODE>::M>& mm,
                                            const Model<typename Types<MODE>::C>& mc, int face, uint32_t line,
-                                           uint32_t st, int n)
+                                           uint32_t st, int n, uint32_t l1, uint32_t l2)
 {
     using S = typename Types<MODE>::S;
     using C = typename Types<MODE>::C;
@@ -204,13 +197,14 @@ __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<
     C a[NV];
     if (kind == BC_PERIODIC) {
         const int gs[2] = {g1, g2};
+        const uint32_t ls[2] = {l1, l2};
 #pragma unroll
         for (int k = 0; k < 2; k++) {
             const int src = ((gs[k] % n) + n) % n;
 #pragma unroll
             for (int i = 0; i < NV; i++)
                 if (k == 0 || vsign(i, axis) == in) a[i] = static_cast<C>((fn + i * sv)[at(src)]);
-            store_layer(fn, sv, at(gs[k]), a, k == 1, axis, in);
+            store_layer(fn, sv, ls[k], a, k == 1, axis, in);
         }
         return;
     }
@@ -227,12 +221,12 @@ __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<
     M c1, m1, c2, m2;
     layer_coefs(kind, 1, c1, m1);
     layer_coefs(kind, 2, c2, m2);
-    const Macro<M> l1 = layer_state(q0, q1, c1, m1, axis);
-    const Macro<M> l2 = layer_state(q0, q1, c2, m2, axis);
-    equilibrium<C, M>(l1, mm, mc, a);
-    store_layer(fn, sv, at(g1), a, false, axis, in);
-    equilibrium<C, M>(l2, mm, mc, a);
-    store_layer(fn, sv, at(g2), a, true, axis, in);
+    const Macro<M> q1s = layer_state(q0, q1, c1, m1, axis);
+    const Macro<M> q2s = layer_state(q0, q1, c2, m2, axis);
+    equilibrium<C, M>(q1s, mm, mc, a);
+    store_layer(fn, sv, l1, a, false, axis, in);
+    equilibrium<C, M>(q2s, mm, mc, a);
+    store_layer(fn, sv, l2, a, true, axis, in);
 }
 
 // Ring slot of plane z + j of velocity I's column at unroll phase K: the
