@@ -17,11 +17,15 @@ Beside it:
                 `traffic` is the counter-measured HBM bytes per launch from
                 the committed rocprofv3 summary when it was taken on this
                 kernel source, else null;
+  copy_ceiling  the rate of a plain copy of the same bytes between two
+                alternating buffers, the practical ceiling of such a kernel;
   periodic_riemann  the 128^3 periodic 3D Riemann problem in FP64, FP32 and
                 FP32 with FP64 temperature: MLUPS, kernel GB/s and the FP32
                 modes' error against the FP64 run;
   batch         64 solves of uneven size, 500 steps each, in one persistent
-                launch per step vs the same solves stepped one after another;
+                launch per step vs the same solves stepped one after another,
+                and vs the plain one-at-a-time FP64 loop (with the batched
+                results' error against it);
   serving       an open Poisson stream of mixed solves through the
                 continuous-batching server vs the plain one-at-a-time FP64
                 loop on the same arrival times: solves/s, p50/p99 time to
@@ -100,15 +104,17 @@ def cpu_baseline(case, steps: int = 3):
             "sample": f"{case.grid[0]}x{case.grid[1]}x{case.grid[2]} full grid, {steps} steps after 1 warm-up, FP64"}
 
 
-def batch_bench(lbm3d, inputs, seed: int, count: int = 64, steps: int = 500):
-    """64 uneven solves: one persistent launch per step vs one solve at a time."""
+def batch_bench(lbm3d, inputs, metrics, seed: int, count: int = 64, steps: int = 500):
+    """64 uneven solves: one persistent launch per step vs one solve at a time,
+    both in FP32 with FP64 temperature recovery, and vs the plain FP64 loop
+    (one solve at a time), with the batched results' error against it."""
     cases = inputs.batch_cases(seed, count=count, steps=steps, precision="fp32_t64")
     sites = sum(c.sites for c in cases)
 
-    def fresh():
+    def fresh(precision=None):
         out = []
         for c in cases:
-            s = lbm3d.Solver(c.params)
+            s = lbm3d.Solver(c.params if precision is None else dict(c.params, precision=precision))
             s.init(*c.fields)
             out.append(s)
         return out
@@ -120,6 +126,7 @@ def batch_bench(lbm3d, inputs, seed: int, count: int = 64, steps: int = 500):
     lbm3d.lbm3d_batch_step([s.h for s in solvers], [steps] * count)
     t_batch = time.perf_counter() - t0
     f_batch = [s.get_f() for s in solvers[:4]]
+    m_batch = [s.moments() for s in solvers]
     for s in solvers:
         s.close()
     solvers = fresh()
@@ -134,12 +141,27 @@ def batch_bench(lbm3d, inputs, seed: int, count: int = 64, steps: int = 500):
     same = all(np.array_equal(a, s.get_f()) for a, s in zip(f_batch, solvers[:4]))
     for s in solvers:
         s.close()
+    # the plain FP64 loop: each solve alone, the same steps (1 + steps, as above)
+    solvers = fresh("fp64")
+    for s in solvers:
+        s.step(1)
+        s.sync()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps)
+        s.sync()
+    t_f64 = time.perf_counter() - t0
+    err = max(metrics.max_rel_l1(a, s.moments()) for a, s in zip(m_batch, solvers))
+    for s in solvers:
+        s.close()
     return {"solves": count, "steps_each": steps, "sites_total": sites, "precision": "fp32_t64",
             "tile": [64, 8, tz], "tile_from": "autotuner",
             "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
             "batched_mlups": round(sites * steps / t_batch / 1e6, 1),
             "sequential_mlups": round(sites * steps / t_seq / 1e6, 1),
-            "speedup": round(t_seq / t_batch, 3), "first4_bitwise_equal_alone": bool(same)}
+            "speedup": round(t_seq / t_batch, 3), "first4_bitwise_equal_alone": bool(same),
+            "fp64_loop_s": round(t_f64, 4), "speedup_vs_fp64_loop": round(t_f64 / t_batch, 3),
+            "max_rel_l1_batched_vs_fp64": float(f"{err:.3e}")}
 
 
 def periodic_riemann_bench(lbm3d, inputs, metrics, seed: int, steps: int = 200):
@@ -304,9 +326,17 @@ def main():
         },
     }
     s.close()
+    # practical ceiling: a plain copy of the step's bytes (the f read per
+    # step), alternating between two buffers as the step does
+    copy_gbs = lbm3d.lbm3d_stream_copy_rate(case.sites * bps // 2, 10)
+    out["copy_ceiling"] = {
+        "what": "plain float4 copy of the bytes one step reads, alternating between two buffers",
+        "GBps": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / PEAK_HBM_GBS, 4),
+        "step_kernel_frac_of_copy": round(achieved / copy_gbs, 4),
+    }
     if not args.no_batch:
         out["periodic_riemann"] = periodic_riemann_bench(lbm3d, inputs, metrics, args.seed)
-        out["batch"] = batch_bench(lbm3d, inputs, args.seed)
+        out["batch"] = batch_bench(lbm3d, inputs, metrics, args.seed)
     if not args.no_serve:
         out["serving"] = serve_bench(lbm3d, inputs, metrics, args.seed)
     if not args.no_cpu_baseline:

@@ -165,6 +165,15 @@ int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t* tz);
 /* Wait for all work enqueued on the handle's stream. */
 int32_t lbm3d_sync(lbm3d_t h);
 
+/* Diagnostic, not part of the scheme: the device's practical streaming
+ * rate for a kernel like the time step.  Copies `bytes` (rounded down to
+ * 16) back and forth between two device buffers it allocates and frees,
+ * one float4 per thread with non-temporal stores, `launches` round trips
+ * after two warm-up ones, timed with HIP events.  *gbs receives the bytes
+ * read plus written per second in GB/s.  Blocking.  E_INVAL for bytes <
+ * 4096, launches < 1 or gbs NULL; E_NOMEM if the buffers do not fit. */
+int32_t lbm3d_stream_copy_rate(int64_t bytes, int32_t launches, double* gbs);
+
 /* (rho, u, p = rho T) on the interior nodes into caller arrays of nx*ny*nz
  * doubles each (any pointer may be NULL to skip that field).  Blocking.
  * Returns E_NONFINITE (after filling the arrays) if the health word has the

@@ -76,6 +76,7 @@ def _load():
         "lbm3d_batch_tune": (I32, [ctypes.POINTER(P), I32, I32, ctypes.POINTER(I32)]),
         "lbm3d_get_tile": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "lbm3d_sync": (I32, [P]),
+        "lbm3d_stream_copy_rate": (I32, [I64, I32, D]),
         "lbm3d_moments": (I32, [P, D, D, D, D, D]),
         "lbm3d_conserved": (I32, [P, D]),
         "lbm3d_status": (I32, [P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(I64)]),
@@ -223,6 +224,14 @@ def lbm3d_tune(h, launches: int = 10):
 
 def lbm3d_sync(h):
     _check(_lib.lbm3d_sync(h), "lbm3d_sync")
+
+
+def lbm3d_stream_copy_rate(nbytes: int, launches: int = 10) -> float:
+    """GB/s (read + written) of a plain copy alternating between two device
+    buffers of nbytes each: the practical ceiling of an HBM-bound kernel."""
+    gbs = ctypes.c_double(0.0)
+    _check(_lib.lbm3d_stream_copy_rate(int(nbytes), int(launches), ctypes.byref(gbs)), "lbm3d_stream_copy_rate")
+    return gbs.value
 
 
 def lbm3d_moments(h, shape, allow_nonfinite: bool = False):

@@ -90,3 +90,13 @@ def test_stable_defaults_and_paper_parameters_are_admitted():
 def test_device_count_is_callable():
     from paper_1010_4135_amd import lbm3d
     assert lbm3d.lbm3d_device_count() >= 0
+
+
+@pytest.mark.parametrize("nbytes,launches", [(0, 1), (4095, 1), (1 << 20, 0)])
+def test_stream_copy_rate_rejects_bad_arguments(nbytes, launches):
+    """The bandwidth diagnostic validates its arguments before any device
+    call (so this runs without a GPU)."""
+    from paper_1010_4135_amd import lbm3d
+    with pytest.raises(lbm3d.LbmError) as ei:
+        lbm3d.lbm3d_stream_copy_rate(nbytes, launches)
+    assert ei.value.code == -1
