@@ -165,6 +165,24 @@ int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t* tz);
 /* Wait for all work enqueued on the handle's stream. */
 int32_t lbm3d_sync(lbm3d_t h);
 
+/* Von Neumann stability analysis of the scheme (Sec. 3, the amplification
+ * matrix G_ij of a Fourier mode about a uniform equilibrium): the largest
+ * eigenvalue modulus max|omega| of G over nk wave numbers k dx spaced evenly
+ * in [kdx_lo, kdx_hi] (nk = 1: kdx_lo only).  q = (rho, ux, uy, uz, T) is
+ * the uniform state (rho, T > 0).  axis 0, 1, 2 puts the wave vector along
+ * x, y or z; 3 gives every axis the same k dx.  alpha_t is the limiter's
+ * linearisation parameter of the NND symbol (|alpha_t| < 1/2; 0 for the
+ * paper's figures).  Uses c1, c2, eta0, gamma, tau, dt, dx and the
+ * no-dissipation flag of p (grid sizes and boundaries must be valid but do
+ * not enter); parameters the step would reject as E_UNSTABLE are analysed
+ * too.  *max_omega receives the maximum and *kdx_at_max (may be NULL) the
+ * k dx where it occurs.  Host computation only, no device work; the
+ * eigenvalue modulus is taken from the growth of G^(2^20), accurate to
+ * about 1e-5.  E_INVAL for bad arguments. */
+int32_t lbm3d_stability(const lbm3d_params* p, const double* q, int32_t axis, double kdx_lo,
+                        double kdx_hi, int32_t nk, double alpha_t, double* max_omega,
+                        double* kdx_at_max);
+
 /* Diagnostic, not part of the scheme: the device's practical streaming
  * rate for a kernel like the time step.  Copies `bytes` (rounded down to
  * 16) back and forth between two device buffers it allocates and frees,

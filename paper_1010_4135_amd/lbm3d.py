@@ -77,6 +77,7 @@ def _load():
         "lbm3d_get_tile": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "lbm3d_sync": (I32, [P]),
         "lbm3d_stream_copy_rate": (I32, [I64, I32, D]),
+        "lbm3d_stability": (I32, [PP, D, I32, ctypes.c_double, ctypes.c_double, I32, ctypes.c_double, D, D]),
         "lbm3d_moments": (I32, [P, D, D, D, D, D]),
         "lbm3d_conserved": (I32, [P, D]),
         "lbm3d_status": (I32, [P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(I64)]),
@@ -224,6 +225,21 @@ def lbm3d_tune(h, launches: int = 10):
 
 def lbm3d_sync(h):
     _check(_lib.lbm3d_sync(h), "lbm3d_sync")
+
+
+def lbm3d_stability(params: dict, q, axis: int = 0, kdx=(0.0, np.pi), nk: int = 64, alpha_t: float = 0.0):
+    """Von Neumann analysis of the scheme about the uniform state
+    q = (rho, ux, uy, uz, T): (max |omega|, k dx where it occurs) over nk
+    wave numbers in [kdx[0], kdx[1]] along `axis` (3: all axes)."""
+    p = make_params(params)
+    qa = np.ascontiguousarray(q, dtype=np.float64)
+    if qa.shape != (5,):
+        raise ValueError("q must hold (rho, ux, uy, uz, T)")
+    om = ctypes.c_double(0.0)
+    kk = ctypes.c_double(0.0)
+    _check(_lib.lbm3d_stability(ctypes.byref(p), _dp(qa), int(axis), float(kdx[0]), float(kdx[1]), int(nk),
+                                float(alpha_t), ctypes.byref(om), ctypes.byref(kk)), "lbm3d_stability")
+    return om.value, kk.value
 
 
 def lbm3d_stream_copy_rate(nbytes: int, launches: int = 10) -> float:

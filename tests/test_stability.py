@@ -1,0 +1,76 @@
+"""Von Neumann stability analysis of the scheme (Sec. 3): the library's
+lbm3d_stability (host code, no GPU) against closed forms and the paper's
+statements about its Figs. 2 and 3."""
+import numpy as np
+import pytest
+
+from paper_1010_4135_amd import inputs, lbm3d
+
+
+def _params(c1, c2, eta0, dx, dt=1e-5, tau=1e-5, flags=0):
+    d = inputs.make_params((8, 8, 8), (0, 0, 0, 0, 0, 0), precision="fp64")
+    d.update(c1=c1, c2=c2, eta0=eta0, gamma=1.4, tau=tau, dt=dt, dx=dx, flags=flags)
+    return d
+
+
+@pytest.mark.parametrize("q", [(1.0, 0.0, 0.0, 0.0, 1.0), (1.3, 0.5, -0.2, 0.1, 2.0), (0.2, 3.0, 1.0, -1.0, 9.0)])
+@pytest.mark.parametrize("dt_tau", [1.0, 0.5, 1.7])
+def test_long_wave_limit_is_neutral(q, dt_tau):
+    """At k = 0 only relaxation acts: G = (1 - dt/tau) I + (dt/tau) df^eq/df,
+    and df^eq/df is a projection onto the 5 conserved moments, so the
+    eigenvalues are 1 (five times) and 1 - dt/tau: max |omega| = 1."""
+    p = _params(8.0, 24.0, 8.0, 1.0 / 256, dt=1e-5, tau=1e-5 / dt_tau)
+    om, _ = lbm3d.lbm3d_stability(p, q, 0, (0.0, 0.0), 1)
+    assert abs(om - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_collisionless_limit_is_first_order_upwind(axis):
+    """With relaxation switched off (tau >> dt) and no dissipation, G is
+    diagonal: each velocity is advected alone by the linearised NND symbol,
+    the first-order upwind factor 1 - c (1 - exp(-i theta)) for c >= 0 and
+    1 - c (exp(i theta) - 1) for c < 0, with c = v_ia dt / dx."""
+    c1, c2, dx, dt = 8.0, 24.0, 1.0 / 64, 2e-4
+    p = _params(c1, c2, 8.0, dx, dt=dt, tau=1e6 * dt, flags=1)
+    cs = [c1 * dt / dx, -c1 * dt / dx, c2 / np.sqrt(3) * dt / dx, -c2 / np.sqrt(3) * dt / dx, 0.0]
+    for th in (0.3, 1.1, 2.0, np.pi):
+        want = max(abs(1 - c * (1 - np.exp(-1j * th))) if c >= 0 else abs(1 - c * (np.exp(1j * th) - 1))
+                   for c in cs)
+        got, _ = lbm3d.lbm3d_stability(p, (1.0, 0.0, 0.0, 0.0, 1.0), axis, (th, th), 1)
+        assert abs(got - want) < 1e-4, (th, got, want)
+
+
+def test_courant_number_above_one_is_unstable():
+    """The upwind factor exceeds 1 once c = c1 dt/dx > 1 (at k dx = pi it is
+    |1 - 2c|); the analysis still runs for parameters the step would refuse."""
+    c1, dx = 8.0, 1.0 / 64
+    dt = 1.2 * dx / c1
+    p = _params(c1, 24.0, 8.0, dx, dt=dt, tau=1e6 * dt, flags=1)
+    got, k = lbm3d.lbm3d_stability(p, (1.0, 0.0, 0.0, 0.0, 1.0), 0, (0.0, np.pi), 33)
+    assert got > 1.3 and abs(k - np.pi) < 1e-12
+
+
+@pytest.mark.parametrize("fig,c,q,no_diss_min", [
+    ("fig2", (4.0, 12.0, 4.0), (1.0, 4.0, 0.0, 0.0, 1.0), 1.005),
+    ("fig3", (20.0, 60.0, 20.0), (1.0, 20.0, 0.0, 0.0, 1.0), 1.03),
+])
+def test_dissipation_makes_the_scheme_stable(fig, c, q, no_diss_min):
+    """Sec. 3, Figs. 2 and 3 (dx = 4e-3, dt = tau = 1e-5, b = 5, alpha = beta
+    = 0): with the dissipation term the largest eigenvalue modulus stays at
+    1 (to the accuracy of this reading), without it the NND scheme grows
+    at short wavelengths."""
+    with_diss, _ = lbm3d.lbm3d_stability(_params(*c, 4e-3), q, 0, (0.0, np.pi), 129)
+    without, k = lbm3d.lbm3d_stability(_params(*c, 4e-3, flags=1), q, 0, (0.0, np.pi), 129)
+    assert with_diss <= 1.001
+    assert without > no_diss_min and without > with_diss
+    assert k > np.pi / 2  # the growing modes are short waves
+
+
+@pytest.mark.parametrize("kw", [dict(axis=4), dict(nk=0), dict(alpha_t=0.5), dict(q=(0.0, 0, 0, 0, 1.0)),
+                                dict(q=(1.0, 0, 0, 0, -1.0))])
+def test_bad_arguments_are_rejected(kw):
+    args = dict(q=(1.0, 0.0, 0.0, 0.0, 1.0), axis=0, kdx=(0.0, np.pi), nk=8, alpha_t=0.0)
+    args.update(kw)
+    with pytest.raises(lbm3d.LbmError) as ei:
+        lbm3d.lbm3d_stability(_params(8.0, 24.0, 8.0, 1.0 / 256), **args)
+    assert ei.value.code == -1
