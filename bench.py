@@ -100,8 +100,15 @@ def cpu_baseline(case, steps: int = 3):
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, one step
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    o.step(1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(used)
     return {"value": round(case.sites * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": used, "kind": "oracle",
-            "sample": f"{case.grid[0]}x{case.grid[1]}x{case.grid[2]} full grid, {steps} steps after 1 warm-up, FP64"}
+            "sample": f"{case.grid[0]}x{case.grid[1]}x{case.grid[2]} full grid, {steps} steps after 1 warm-up, FP64",
+            "single_thread_value": round(case.sites / dt1 / 1e6, 3)}
 
 
 def batch_bench(lbm3d, inputs, metrics, seed: int, count: int = 64, steps: int = 500):
