@@ -303,3 +303,12 @@ def test_autotuner_keeps_state_and_is_remembered():
     b.init(*case.fields)
     b.step(17)
     assert np.array_equal(a.get_f(), b.get_f())
+
+
+def test_stream_copy_rate_is_plausible():
+    """The bandwidth diagnostic behind bench.py's copy ceiling: a copy of
+    512 MB (twice the Infinity Cache) between alternating buffers runs
+    somewhere between 0.5 and 10 TB/s (read + written) on the 8 TB/s
+    device."""
+    gbs = _lib().lbm3d_stream_copy_rate(512 << 20, 5)
+    assert 500.0 < gbs < 10000.0, gbs
