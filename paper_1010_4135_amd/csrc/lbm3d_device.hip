@@ -121,6 +121,11 @@ k_step(Grid g, Model<double> md, Model<float> mf, const typename Types<MODE>::S*
 #ifndef LBM3D_BATCH_VK
 #define LBM3D_BATCH_VK 1
 #endif
+// LBM3D_BATCH_KEEP: the batched step keeps each tile's solve parameters in
+// registers (1) or lets the compiler re-load them from the table (0).
+#ifndef LBM3D_BATCH_KEEP
+#define LBM3D_BATCH_KEEP 1
+#endif
 
 template <int MODE, int BY>
 __global__ void __launch_bounds__(TILE_X * BY) LBM3D_TILED_ATTR
@@ -148,6 +153,23 @@ k_step_tiled(StepArgs<MODE> A, Model<double> md, Model<float> mf, int ntx, int n
 // many solves (any sizes, one precision), each tile advanced by the same
 // step_tile body as a single solve, so every solve's result is bitwise the
 // same alone or in any batch.
+// A uniform value the optimiser may not re-derive: it stays in a scalar
+// register (or a spill slot) rather than being loaded again from the
+// read-only table it came from.
+template <typename T>
+__device__ __forceinline__ void keep(T& v)
+{
+    asm volatile("" : "+s"(v));
+}
+template <typename T>
+__device__ __forceinline__ void keep_model(Model<T>& m)
+{
+    keep(m.c1); keep(m.k); keep(m.c1sq); keep(m.c2sq); keep(m.e0sq); keep(m.inv_b); keep(m.r_aT);
+    keep(m.x_a0); keep(m.x_aT); keep(m.x_au); keep(m.x_b0); keep(m.x_bT); keep(m.x_bu); keep(m.x_d);
+    keep(m.d_a0); keep(m.d_aT); keep(m.d_au); keep(m.d_b0); keep(m.d_bT); keep(m.d_bu); keep(m.d_d);
+    keep(m.k_adv); keep(m.k_bgk); keep(m.k_lap0); keep(m.k_lap1); keep(m.a1); keep(m.ad);
+}
+
 template <int MODE, int BY>
 __global__ void __launch_bounds__(TILE_X * BY) LBM3D_TILED_ATTR
 k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict__ tiles, int ntiles, int parity)
@@ -166,7 +188,17 @@ k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict_
         A.health = d.health;
 #pragma unroll
         for (int k = 0; k < 10; k++) A.xin[k / 5][k % 5] = d.xin[k / 5][k % 5];
-        step_tile<MODE, BY, LBM3D_BATCH_VK>(A, d.md, d.mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
+        Model<double> md = d.md;
+        Model<float> mf = d.mf;
+#if LBM3D_BATCH_KEEP
+        // the tile's solve is read once per tile: without this the compiler
+        // re-loads its constants and strides from the table in every plane,
+        // each a scalar-memory round trip the plane then waits for
+        keep(A.g.sy); keep(A.g.sz); keep(A.g.sv); keep(A.g.org); keep(A.g.sink); keep(A.g.xg);
+        keep(A.f); keep(A.fn);
+        keep_model(mf);
+#endif
+        step_tile<MODE, BY, LBM3D_BATCH_VK>(A, md, mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
         lds_barrier();  // the plane buffers are reused by the next tile
     }
 }

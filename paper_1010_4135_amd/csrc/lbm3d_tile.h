@@ -446,7 +446,11 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     S hrow[2][NK];
     S hcolv[2] = {S(0), S(0)};
     auto load_halo = [&](int set, int zz) {
-        hcolv[set] = hptr[(int64_t)zz * sz];
+        // (through a global-space pointer: a generic one, as the batched
+        // step's table-loaded f would give, becomes a flat load, which the
+        // LDS waits would then wait for as well)
+        using GP = const __attribute__((address_space(1))) S*;
+        hcolv[set] = reinterpret_cast<GP>(reinterpret_cast<uint64_t>(hptr))[(int64_t)zz * sz];
 #pragma unroll
         for (int k = 0; k < NK; k++) {
             const int i = kHaloJobs.e[wave + k * BY] >> 2;
