@@ -289,8 +289,8 @@ __device__ __forceinline__ void layer_job(const StepArgs<MODE>& A, const Model<d
             q.T = static_cast<M>(fx->q[face][4]);
             C e[NV];
             equilibrium<C, M>(q, pick<M>(md, mf), pick<C>(md, mf), e);
-            store_node(A.fn, g.sv, l1, e);
-            store_node(A.fn, g.sv, l2, e);
+            store_node(gptr(A.fn), g.sv, l1, e);
+            store_node(gptr(A.fn), g.sv, l2, e);
         } else {
             layer_line<MODE>(A, pick<M>(md, mf), pick<C>(md, mf), face, line, st, n, l1, l2);
         }

@@ -155,9 +155,20 @@ __device__ __forceinline__ Macro<M> layer_state(const Macro<M>& a, const Macro<M
     return q;
 }
 
-template <typename S, typename C>
-__device__ __forceinline__ void store_node(S* __restrict__ fn, int64_t sv, uint32_t off, const C (&v)[NV])
+// A pointer into the distribution array as a global-space pointer: where
+// the array's address comes from a table in memory rather than a kernel
+// argument the compiler cannot tell it is global and would emit flat
+// accesses, which every LDS wait then also waits for.
+template <typename S>
+__device__ __forceinline__ __attribute__((address_space(1))) S* gptr(S* p)
 {
+    return reinterpret_cast<__attribute__((address_space(1))) S*>(reinterpret_cast<uint64_t>(p));
+}
+
+template <typename P, typename C>
+__device__ __forceinline__ void store_node(P fn, int64_t sv, uint32_t off, const C (&v)[NV])
+{
+    using S = typename std::remove_reference<decltype(*fn)>::type;
 #pragma unroll
     for (int i = 0; i < NV; i++) (fn + i * sv)[off] = static_cast<S>(v[i]);
 }
@@ -166,13 +177,13 @@ __device__ __forceinline__ void store_node(S* __restrict__ fn, int64_t sv, uint3
 // stencil, the second only by the velocities advected into the grid through
 // that face (sign `in` along the axis), whose NND flux reaches two nodes
 // upwind.  Only those values are written.
-template <typename S, typename C>
-__device__ __forceinline__ void store_layer(S* __restrict__ fn, int64_t sv, uint32_t off, const C (&v)[NV],
+template <typename P, typename C>
+__device__ __forceinline__ void store_layer(P fn, int64_t sv, uint32_t off, const C (&v)[NV],
                                             bool second, int axis, int in)
 {
 #pragma unroll
     for (int i = 0; i < NV; i++)
-        if (!second || vsign(i, axis) == in) (fn + i * sv)[off] = static_cast<S>(v[i]);
+        if (!second || vsign(i, axis) == in) (fn + i * sv)[off] = v[i];
 }
 
 // Boundary layers of one face on the line of nodes through `line` (offset
@@ -189,7 +200,7 @@ __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<
     using C = typename Types<MODE>::C;
     using M = typename Types<MODE>::M;
     const int64_t sv = A.g.sv;
-    S* __restrict__ fn = A.fn;
+    const auto fn = gptr(A.fn);
     const int side = face & 1, kind = A.bc.kind[face], axis = face >> 1;
     const int g1 = side ? n : -1, g2 = side ? n + 1 : -2;  // wall / first layer, second layer
     const int in = side ? -1 : 1;
