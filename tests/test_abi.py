@@ -61,6 +61,9 @@ def test_footprint_counts_both_buffers():
 
 @pytest.mark.parametrize("kw,code", [
     (dict(grid=(0, 4, 4)), -1),
+    (dict(grid=((1 << 20) + 1, 4, 4)), -1),  # a side above 2^20 nodes
+    (dict(grid=(4, 4, 65536)), -1),          # nz above 65535 (the z index of a batch tile)
+    (dict(grid=(1 << 16, 1 << 12, 8)), -1),  # one velocity plane beyond 32-bit element offsets
     (dict(c1=0.0), -1),
     (dict(c2=8.0), -1),                      # c1 == c2
     (dict(eta0=-1.0), -1),
