@@ -36,6 +36,7 @@ Beside it:
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S]
                   [--no-batch] [--no-serve] [--no-cpu-baseline] [--copy-check]
+                  [--batch-only]
 """
 from __future__ import annotations
 
@@ -283,6 +284,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run the checkpoint pack (a plain copy of 15 x nodes elements) for counter calibration")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched step of the 64-solve mix (--steps steps) and print its rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -290,6 +293,27 @@ def main():
         sys.exit(2)
 
     from paper_1010_4135_amd import inputs, lbm3d, metrics
+
+    if args.batch_only:
+        # the batched step alone (for a profiler): the 64-solve mix, the
+        # tuner's tile depth, one warm-up step, then --steps batched steps
+        cases = inputs.batch_cases(args.seed, count=64, steps=args.steps, precision="fp32_t64")
+        sites = sum(c.sites for c in cases)
+        solvers = []
+        for c in cases:
+            s = lbm3d.Solver(c.params)
+            s.init(*c.fields)
+            solvers.append(s)
+        tz = lbm3d.lbm3d_batch_tune([s.h for s in solvers], 5)
+        lbm3d.lbm3d_batch_step([s.h for s in solvers], [1] * len(solvers))
+        t0 = time.perf_counter()
+        lbm3d.lbm3d_batch_step([s.h for s in solvers], [args.steps] * len(solvers))
+        dt = time.perf_counter() - t0
+        for s in solvers:
+            s.close()
+        print(json.dumps({"batch_only": True, "solves": len(cases), "sites_total": sites, "steps": args.steps,
+                          "tile": [64, 8, tz], "batched_mlups": round(sites * args.steps / dt / 1e6, 1)}), flush=True)
+        return
 
     case = inputs.shock_bubble(args.seed, precision=args.precision)
     nx, ny, nz = case.grid
