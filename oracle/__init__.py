@@ -27,6 +27,7 @@ _LIB = os.path.join(_HERE, "liblbm3d_oracle.so")
 NV = 15
 PERIODIC, OUTFLOW, INFLOW, REFLECT = 0, 1, 2, 3
 NO_DISSIPATION = 1
+UPWIND2 = 2
 
 
 def build(force: bool = True) -> str:

@@ -18,6 +18,9 @@
  *   - NND flux with f^+ / f^- splitting, minmod .... Sec. 3, Eq. (nnd) ff.
  *   - artificial dissipation lambda_i Lap f ......... Sec. 3, Eq. (lp)
  *   - explicit forward-Euler time advance ........... Sec. 3, Eq. (fi1)
+ *   - (variant) the second-order upwind difference of the original
+ *     Kataoka-Tsutahara scheme in place of NND ...... Sec. 3, opening
+ *     paragraph; Sec. 4 (1a), Fig. 6
  *   - boundary nodes (fixed state, linear extrapolation, reflection)
  *                                                    Sec. 4 (2), shock-bubble
  * Readings where the paper is silent are listed at each place they are used.
@@ -40,7 +43,7 @@
 #define NG 2
 
 enum { ORC_PERIODIC = 0, ORC_OUTFLOW = 1, ORC_INFLOW = 2, ORC_REFLECT = 3 };
-enum { ORC_NO_DISSIPATION = 1u };
+enum { ORC_NO_DISSIPATION = 1u, ORC_UPWIND2 = 2u };
 
 typedef struct {
     int32_t nx, ny, nz;
@@ -294,7 +297,20 @@ static void step_once(orc_state* s)
                         double fR_m = fm[2] - 0.5 * minmod(fm[2] - fm[1], fm[3] - fm[2]);
                         double h_p = fL_p + fR_p;
                         double h_m = fL_m + fR_m;
-                        conv += (h_p - h_m) / dx;
+                        if (p->flags & ORC_UPWIND2) {
+                            /* second-order upwind difference of the original
+                             * scheme: v (3 f_I - 4 f_{I-1} + f_{I-2}) / (2 dx)
+                             * for v > 0, v (-3 f_I + 4 f_{I+1} - f_{I+2}) /
+                             * (2 dx) for v < 0 */
+                            double fI2[5];
+                            for (int k = -2; k <= 2; k++) fI2[k + 2] = f[I + k * stride[a]];
+                            if (va > 0.0)
+                                conv += va * (3.0 * fI2[2] - 4.0 * fI2[1] + fI2[0]) / (2.0 * dx);
+                            else if (va < 0.0)
+                                conv += va * (-3.0 * fI2[2] + 4.0 * fI2[3] - fI2[4]) / (2.0 * dx);
+                        } else {
+                            conv += (h_p - h_m) / dx;
+                        }
                         lap += (f[I + stride[a]] - 2.0 * fI + f[I - stride[a]]) / (dx * dx);
                     }
                     double lam = (p->flags & ORC_NO_DISSIPATION) ? 0.0 : s->lam[i];

@@ -443,3 +443,128 @@ def test_single_node_impulse_response(i):
     np.testing.assert_allclose(got, exp, rtol=0, atol=1e-13 * np.abs(f0).max())
     # the response is not negligible against that tolerance
     assert np.abs(got - f0).max() > 1e-6 * np.abs(f0).max()
+
+
+# --------------------------------------------------- second-order upwind --
+# The paper's comparison scheme (Sec. 3, opening paragraph; Sec. 4 (1a),
+# Fig. 6): the original Kataoka-Tsutahara convection term, a second-order
+# upwind difference, in place of NND.
+
+
+@pytest.mark.parametrize("i", range(1, 15))
+def test_upwind2_single_node_impulse_response(i):
+    """One distribution raised by eps at one node of a uniform equilibrium,
+    one step with the second-order upwind difference: along each axis with
+    v_ia != 0 the raised node loses 3/2 a eps, the next node downwind gains
+    2 a eps and the one after loses a eps / 2 (a = dt |v_ia| / dx, the
+    weights 3, -4, 1 over 2 dx of the one-sided difference); dissipation and
+    relaxation as in the NND impulse test; nothing else changes."""
+    prm = inputs.make_params((9, 9, 9), (0,) * 6, tau=2e-5, flags=oracle.UPWIND2)
+    c1, c2, eta0, gamma = prm["c1"], prm["c2"], prm["eta0"], prm["gamma"]
+    dt, dx, tau = prm["dt"], prm["dx"], prm["tau"]
+    v, _ = oracle.velocities(c1, c2, eta0)
+    lam = [c1 * dx] + [c1 * dx / 10.0] * 6 + [0.0] * 8
+    shape = (9, 9, 9)
+    rho, ux, uy, uz, T = 1.1, 0.3, -0.2, 0.1, 1.2
+    o = oracle.Oracle(prm)
+    o.init(*(np.full(shape, a) for a in (rho, ux, uy, uz, rho * T)))
+    f0 = o.get_f()
+    I = np.array([4, 4, 4])
+    eps = 0.01 * f0[(i,) + tuple(I)]
+    f = f0.copy()
+    f[(i,) + tuple(I)] += eps
+    o.set_f(f)
+    o.step(1)
+    got = o.get_f()
+    exp = f0.copy()
+    for a in range(3):
+        e = np.zeros(3, dtype=int)
+        e[2 - a] = 1
+        for s in (1, -1):
+            exp[(i,) + tuple(I + s * e)] += dt * lam[i] * eps / dx ** 2
+        if v[i, a] != 0.0:
+            s = 1 if v[i, a] > 0 else -1
+            aa = dt * abs(v[i, a]) / dx
+            exp[(i,) + tuple(I + s * e)] += 2.0 * aa * eps
+            exp[(i,) + tuple(I + 2 * s * e)] -= 0.5 * aa * eps
+    fI = f[(slice(None),) + tuple(I)]
+    q = oracle.moments_of(c1, c2, eta0, gamma, fI)
+    feq = oracle.equilibrium(c1, c2, eta0, gamma, *q)
+    exp[(slice(None),) + tuple(I)] = fI - dt / tau * (fI - feq)
+    exp[(i,) + tuple(I)] -= 6 * dt * lam[i] * eps / dx ** 2 + 1.5 * dt * np.abs(v[i]).sum() * eps / dx
+    np.testing.assert_allclose(got, exp, rtol=0, atol=1e-13 * np.abs(f0).max())
+
+
+@pytest.mark.parametrize("i", [1, 2, 8, 13])
+def test_upwind2_spatial_operator_is_second_order(i):
+    """Free streaming of a smooth profile (no relaxation: tau >> dt; no
+    dissipation): the one-step change of f_i divided by dt approximates
+    -v_ix df_i/dx, and its error falls four-fold per halving of dx, the
+    order of the second-order upwind difference.  NND, whose limiter
+    flattens the extrema, converges more slowly on the same profile."""
+    def err(n, flags):
+        dx = 1.0 / n
+        prm = inputs.make_params((n, 1, 1), (0,) * 6, dx=dx, tau=1e9, dt=1e-6, flags=flags)
+        x = (np.arange(n) + 0.5) * dx
+        o = oracle.Oracle(prm)
+        ones = np.ones((1, 1, n))
+        o.init(ones, 0.2 * ones, 0 * ones, 0 * ones, ones)
+        f = o.get_f()
+        delta = 1e-3 * f[i].mean()
+        f[i] += delta * np.sin(2 * np.pi * x)[None, None, :]
+        o.set_f(f)
+        o.step(1)
+        rate = (o.get_f()[i] - f[i])[0, 0] / prm["dt"]
+        v, _ = oracle.velocities(prm["c1"], prm["c2"], prm["eta0"])
+        exact = -v[i, 0] * delta * 2 * np.pi * np.cos(2 * np.pi * x)
+        return np.abs(rate - exact).max() / np.abs(exact).max()
+
+    up2 = [err(n, oracle.UPWIND2 | oracle.NO_DISSIPATION) for n in (32, 64, 128)]
+    nnd = [err(n, oracle.NO_DISSIPATION) for n in (32, 64, 128)]
+    for a, b in zip(up2, up2[1:]):
+        assert 3.5 < a / b < 4.5, up2
+    assert up2[-1] < 5e-3
+    assert nnd[-1] > 2 * up2[-1], (nnd, up2)
+
+
+def test_upwind2_conserves_on_periodic_boxes():
+    """The second-order upwind difference is in flux form (flux
+    v (3 f_I - f_{I-1}) / 2 at I + 1/2 for v > 0), so it telescopes: the
+    totals are conserved to rounding as with NND."""
+    case = inputs.smooth_periodic(12, grid=(16, 12, 10), amp=0.2)
+    case.params = dict(case.params, flags=oracle.UPWIND2)
+    o, c0 = _run(case, 30)
+    c1 = o.conserved()
+    scale = _abs_scale(o, case.params)
+    assert np.all(np.abs(c1 - c0) <= 1e-14 * 30 * scale), (c1 - c0) / scale
+
+
+def test_upwind2_oscillates_more_than_nnd_on_the_lax_tube():
+    """Sec. 4 (1a), Fig. 6: on the Lax shock tube without the dissipation
+    term, (2, 6, 2), dx = 0.003, dt = tau = 1e-5, t = 0.1, the second-order
+    upwind scheme oscillates at the discontinuities and NND much less: the
+    total variation of rho in excess of the exact solution's is several
+    times larger with the upwind difference."""
+    g = GOLDEN["lax_tube"]
+    L = (g["left"]["rho"], g["left"]["u"], g["left"]["rho"] * g["left"]["T"])
+    R = (g["right"]["rho"], g["right"]["u"], g["right"]["rho"] * g["right"]["T"])
+    nx, dx = 400, g["dx"]
+    xs = (np.arange(nx) + 0.5) * dx
+    x0 = nx * dx / 2
+    steps = int(round(g["t"] / g["dt"]))
+    ex = riemann.profile(L, R, g["gamma"], xs, x0, steps * g["dt"])
+    tv_exact = np.abs(np.diff(ex[0])).sum()
+    excess = {}
+    for name, flags in (("nnd", oracle.NO_DISSIPATION), ("upwind2", oracle.NO_DISSIPATION | oracle.UPWIND2)):
+        prm = inputs.make_params((nx, 1, 1), (1, 1, 0, 0, 0, 0), dx=dx, c1=g["c1"], c2=g["c2"], eta0=g["eta0"],
+                                 gamma=g["gamma"], dt=g["dt"], tau=g["tau"], flags=flags)
+        left = (xs < x0)[None, None, :]
+        f = [np.where(left, L[k], R[k]) * np.ones((1, 1, nx)) for k in range(3)]
+        z = np.zeros((1, 1, nx))
+        o = oracle.Oracle(prm)
+        o.init(f[0], f[1], z, z, f[2])
+        o.step(steps)
+        rho = o.moments()[0][0, 0]
+        assert np.all(np.isfinite(rho))
+        excess[name] = np.abs(np.diff(rho)).sum() - tv_exact
+    assert excess["upwind2"] > 3.0 * max(excess["nnd"], 1e-3 * tv_exact), excess
