@@ -69,7 +69,11 @@ enum {
 
 /* params.flags bits */
 enum {
-    LBM3D_NO_DISSIPATION = 1u /* drop the artificial dissipation term (lambda_i = 0), the paper's comparison variant */
+    LBM3D_NO_DISSIPATION = 1u, /* drop the artificial dissipation term (lambda_i = 0), the paper's comparison variant */
+    LBM3D_UPWIND2 = 2u,        /* convection by the second-order upwind difference of the original scheme
+                                  (Sec. 3, opening paragraph; Fig. 6) instead of NND: steps run untiled, and
+                                  the batched step and servers refuse such solves */
+    LBM3D_CHECK_STABILITY = 4u /* lbm3d_init refuses (E_UNSTABLE) an initial state lbm3d_admit refuses */
 };
 
 /* health bits reported by lbm3d_status (sticky since init) */
@@ -90,7 +94,7 @@ typedef struct {
     int32_t bc[6];        /* faces -x, +x, -y, +y, -z, +z: LBM3D_PERIODIC .. LBM3D_REFLECT */
     double inflow[6][5];  /* (rho, ux, uy, uz, p) per LBM3D_INFLOW face; ignored elsewhere */
     int32_t precision;    /* LBM3D_FP64, LBM3D_FP32 or LBM3D_FP32_T64 */
-    uint32_t flags;       /* LBM3D_NO_DISSIPATION */
+    uint32_t flags;       /* LBM3D_NO_DISSIPATION | LBM3D_UPWIND2 | LBM3D_CHECK_STABILITY */
 } lbm3d_params;
 
 typedef struct lbm3d_solver* lbm3d_t;
@@ -125,7 +129,9 @@ int32_t lbm3d_set_stream(lbm3d_t h, void* hip_stream);
 /* Initial state: f_i = f_i^eq(rho, u, T = p/rho) on every interior node
  * (the paper states initial macroscopic fields only), then the boundary
  * layers.  E_INVAL if any rho <= 0 or p <= 0 or a value is not finite.
- * Resets the step counter and the health word.  Blocking. */
+ * With LBM3D_CHECK_STABILITY in params.flags, E_UNSTABLE (and nothing
+ * changed) if lbm3d_admit refuses the state.  Resets the step counter and
+ * the health word.  Blocking. */
 int32_t lbm3d_init(lbm3d_t h, const double* rho, const double* ux, const double* uy,
                    const double* uz, const double* p);
 
@@ -173,8 +179,10 @@ int32_t lbm3d_sync(lbm3d_t h);
  * x, y or z; 3 gives every axis the same k dx.  alpha_t is the limiter's
  * linearisation parameter of the NND symbol (|alpha_t| < 1/2; 0 for the
  * paper's figures).  Uses c1, c2, eta0, gamma, tau, dt, dx and the
- * no-dissipation flag of p (grid sizes and boundaries must be valid but do
- * not enter); parameters the step would reject as E_UNSTABLE are analysed
+ * no-dissipation and second-order-upwind flags of p (with LBM3D_UPWIND2 the
+ * convection symbol is (3 - 4 e^{-ik dx} + e^{-2ik dx}) / 2, mirrored for
+ * v < 0; grid sizes and boundaries must be valid but do not enter);
+ * parameters the step would reject as E_UNSTABLE are analysed
  * too.  *max_omega receives the maximum and *kdx_at_max (may be NULL) the
  * k dx where it occurs.  Host computation only, no device work; the
  * eigenvalue modulus is taken from the growth of G^(2^20), accurate to
@@ -182,6 +190,19 @@ int32_t lbm3d_sync(lbm3d_t h);
 int32_t lbm3d_stability(const lbm3d_params* p, const double* q, int32_t axis, double kdx_lo,
                         double kdx_hi, int32_t nk, double alpha_t, double* max_omega,
                         double* kdx_at_max);
+
+/* Stability admission of an initial state (the von Neumann analysis of
+ * Sec. 3 with the paper's rule of thumb turned into a check): the largest
+ * max |omega| of lbm3d_stability over k dx in [0, pi] (33 points, alpha_t =
+ * 0) along x, y, z and the diagonal, at the fastest node (largest |u|), the
+ * coldest and the hottest node of the initial fields (host FP64, nx*ny*nz
+ * each, as lbm3d_init) and at every fixed inflow state.  Returns LBM3D_OK
+ * if it is at most 1 + 1e-3 (the paper calls its Fig. 3 setting, 1.0009 in
+ * this analysis, stable), else E_UNSTABLE; *max_omega (may be NULL)
+ * receives it.  Host only.  E_INVAL / E_UNSTABLE from parameter validation
+ * as lbm3d_create; E_INVAL for rho <= 0 or p <= 0. */
+int32_t lbm3d_admit(const lbm3d_params* p, const double* rho, const double* ux, const double* uy,
+                    const double* uz, const double* pr, double* max_omega);
 
 /* Diagnostic, not part of the scheme: the device's practical streaming
  * rate for a kernel like the time step.  Copies `bytes` (rounded down to
@@ -206,6 +227,13 @@ int32_t lbm3d_conserved(lbm3d_t h, double out[5]);
 /* Health bits (LBM3D_HEALTH_*) accumulated since init, and steps done. */
 int32_t lbm3d_status(lbm3d_t h, uint32_t* health, int64_t* steps_done);
 
+/* Debug aid: fill the buffer the next step writes (interior, boundary
+ * layers and padding) with NaN, then restore its fixed-state layers (which
+ * the steps never rewrite).  A correct step reads nothing it has not
+ * written, so the results stay bitwise the same; a stale read shows up as
+ * NaN.  Blocking.  E_STATE before lbm3d_init. */
+int32_t lbm3d_poison_next(lbm3d_t h);
+
 /* Checkpoint: the interior distributions as [15][nz][ny][nx] in storage
  * precision (double for FP64, float otherwise); bytes must equal
  * 15*nx*ny*nz*elem.  Velocity order: rest; c1 (+x, -x, +y, -y, +z, -z);
@@ -218,22 +246,49 @@ int32_t lbm3d_get_f(lbm3d_t h, void* host, size_t bytes);
 int32_t lbm3d_set_f(lbm3d_t h, const void* host, size_t bytes);
 
 /* Advance `count` independent solves (any mix of sizes, all of the same
- * precision) by nsteps[k] steps each.  Each step of the group is one launch
- * of a persistent kernel over a packed queue of tiles from every solve that
- * still has steps to do; groups of steps are replayed from captured HIP
- * graphs.  Results are bitwise identical to stepping each solve alone.
- * Blocking.  E_INVAL for mixed precisions, duplicate handles, count < 1,
- * or a solve whose velocity plane (about nx*ny*nz elements) reaches 2 GiB:
- * the batched kernel addresses a plane with 32-bit offsets. */
+ * precision) by nsteps[k] steps each: the time step of Sec. 3, Eqs. (nnd),
+ * (lp), (fi1), applied to every member.  Each step of the group is one
+ * launch of a persistent kernel whose workgroups take 64 x BY x TZ tiles of
+ * every solve that still has steps to do from per-XCD work lists (see
+ * lbm3d_batch_plan); groups of steps are replayed from captured HIP graphs.
+ * Results are bitwise identical to stepping each solve alone.  Blocking.
+ * E_INVAL for mixed precisions, duplicate or NULL handles, count < 1, a
+ * negative step count, or a solve whose velocity plane (about nx*ny*nz
+ * elements) reaches 2 GiB: the batched kernel addresses a plane with 32-bit
+ * offsets.  E_STATE if a member is not initialised. */
 int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* nsteps);
 
+/* Work plan of the batched step, computed on the host (no device work): the
+ * tiles of solves with parameters ps[0..count-1] (validated as lbm3d_create,
+ * all of one precision) at tile depth tz (<= 0: the tuned or default depth;
+ * a depth at or beyond a solve's nz gives whole columns), for a device of
+ * `cus` compute units.  Tiles are 64 x BY nodes in x-y (BY = 4 in FP64, 8
+ * otherwise).  Each solve's tiles are cut into contiguous row slabs, the
+ * slabs are dealt to up to 8 lists (one per XCD) largest first onto the
+ * least-loaded list, and each list runs its deepest tiles first.
+ * *ntiles, *nlists and *nblocks (persistent workgroups, a multiple of the
+ * list count) may be NULL.  If `tiles` is not NULL it receives, list by
+ * list, 7 int32 per tile: solve index, x0, x1, y0, y1, z0, z1 (node ranges
+ * [x0, x1) etc.); `cap` is its room in tiles (E_NOMEM if too small).
+ * list_first (9 int32, may be NULL) receives the list boundaries in tiles.
+ * E_INVAL / E_UNSTABLE as lbm3d_create, E_INVAL for mixed precisions. */
+int32_t lbm3d_batch_plan(const lbm3d_params* ps, int32_t count, int32_t tz, int32_t cus, int32_t* ntiles,
+                         int32_t* nlists, int32_t* nblocks, int32_t* tiles, int64_t cap, int32_t* list_first);
+
 /* Autotuner of the batched step: times the persistent launch over the given
- * solves (same rules as lbm3d_batch_step) for tile depths 8, 16 and 32, over
- * `launches` launches each (<= 0: 5), recomputing the same next level each
- * time (states unchanged), and keeps the fastest depth for every later
- * batched step (lbm3d_batch_step and servers) of that precision in this
- * process.  Blocking.  *tz (may be NULL) receives the depth. */
+ * solves (same rules as lbm3d_batch_step) for tile depths 16, 32, 64 and 128
+ * (a depth at or beyond a solve's nz gives whole columns), over `launches`
+ * launches each (<= 0: 5), recomputing the same next level each time
+ * (states unchanged), and keeps the fastest depth for every later batched
+ * step (lbm3d_batch_step and servers) of that precision in this process.
+ * Blocking.  *tz (may be NULL) receives the depth. */
 int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches, int32_t* tz);
+
+/* Tile depth of later batched steps (lbm3d_batch_step, servers) of one
+ * precision in this process, as the autotuner would set it; 0 restores the
+ * default (32).  Results do not depend on it.  E_INVAL for a bad precision
+ * or tz outside [0, 65535]. */
+int32_t lbm3d_batch_set_depth(int32_t precision, int32_t tz);
 
 /* ------------------------------------------------------------- serving --- */
 typedef struct lbm3d_server* lbm3d_server_t;
@@ -249,7 +304,8 @@ typedef struct {
  * running, keeps their state resident on the device, advances all active
  * solves together in batched ticks (continuous batching: solves admitted
  * between ticks join the next one), and completes a ticket when its solve
- * has done its steps.  Solves of any precision may be mixed; each tick
+ * has done its steps, or early, with E_NONFINITE, after the first tick that
+ * leaves it non-finite.  Solves of any precision may be mixed; each tick
  * groups them by precision. */
 int32_t lbm3d_server_create(size_t hbm_budget_bytes, int32_t max_active, lbm3d_server_t* out);
 
@@ -271,9 +327,27 @@ int32_t lbm3d_server_poll(lbm3d_server_t s, uint64_t ticket, int32_t* done);
 
 /* Block until the ticket completes, copy its (rho, u, p) into caller arrays
  * (any may be NULL) and its timing into *t (may be NULL), then forget the
- * ticket.  Returns the solve's own status (E_NONFINITE, E_CANCELLED, ...). */
+ * ticket.  Returns the solve's own status (E_NONFINITE, E_CANCELLED, ...).
+ * One thread may wait on a ticket: a second concurrent waiter gets E_STATE,
+ * and a wait after the ticket was collected gets E_NOTFOUND. */
 int32_t lbm3d_server_wait(lbm3d_server_t s, uint64_t ticket, double* rho, double* ux,
                           double* uy, double* uz, double* p, lbm3d_timing* t);
+
+/* Counters of a server since its creation (a snapshot). */
+typedef struct {
+    int64_t ticks;      /* batched ticks run */
+    int64_t rebuilds;   /* work plans rebuilt for a changed membership */
+    int64_t admitted;   /* solves admitted */
+    int64_t completed;  /* solves finished (done, failed or evicted) */
+    int64_t evicted;    /* solves stopped before their last step because they went non-finite */
+    double wall_s;      /* seconds since the server was created */
+    double busy_s;      /* device time of the ticks' launches (HIP events around each tick) */
+    double admit_s;     /* host time creating and initialising admitted solves */
+    double plan_s;      /* host time rebuilding work plans (planning and table upload) */
+    double finish_s;    /* host time reading back and freeing finished solves */
+} lbm3d_server_counters;
+
+int32_t lbm3d_server_stats(lbm3d_server_t s, lbm3d_server_counters* out);
 
 /* Cancel a queued or running ticket; a later wait returns E_CANCELLED. */
 int32_t lbm3d_server_cancel(lbm3d_server_t s, uint64_t ticket);

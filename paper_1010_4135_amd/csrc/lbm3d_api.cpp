@@ -10,13 +10,6 @@
 #include <new>
 #include <vector>
 
-// Build-time layout knob: 1 = one cache line of padding per row shared by
-// the layer nodes of two rows; 0 = the layers of each row in lines of
-// their own.
-#ifndef LBM3D_SHARED_GHOST_LINE
-#define LBM3D_SHARED_GHOST_LINE 1
-#endif
-
 using namespace lbm3d;
 
 namespace lbm3d {
@@ -47,7 +40,7 @@ int32_t validate(const lbm3d_params* p)
     if (!std::isfinite(p->gamma) || !(p->gamma > 1.0)) return LBM3D_E_INVAL;
     if (!finite_pos(p->tau) || !finite_pos(p->dt) || !finite_pos(p->dx)) return LBM3D_E_INVAL;
     if (p->precision < LBM3D_FP64 || p->precision > LBM3D_FP32_T64) return LBM3D_E_INVAL;
-    if (p->flags & ~(uint32_t)LBM3D_NO_DISSIPATION) return LBM3D_E_INVAL;
+    if (p->flags & ~(uint32_t)(LBM3D_NO_DISSIPATION | LBM3D_UPWIND2 | LBM3D_CHECK_STABILITY)) return LBM3D_E_INVAL;
     for (int face = 0; face < 6; face++) {
         if (p->bc[face] != LBM3D_INFLOW) continue;
         const double* s = p->inflow[face];
@@ -133,14 +126,10 @@ Grid make_grid(const lbm3d_params* p)
     // dense rows: the interior only, rows start on a line (nx is a multiple
     // of 64 elements); otherwise the x layers pad the rows
     const int64_t ox = dense ? 0 : line;
-#if LBM3D_SHARED_GHOST_LINE
     // one cache line of padding per row, holding the two right layer nodes
     // of the row (its first elements) and the two left layer nodes of the
     // next row (its last elements); interior rows start on a line
     const int64_t mxp = (p->nx + line - 1) / line * line + line;
-#else
-    const int64_t mxp = ((ox + p->nx + NG) + line - 1) / line * line;
-#endif
     const int64_t mx = dense ? p->nx : mxp;
     const int64_t my = p->ny + 2 * NG;
     const int64_t mz = p->nz + 2 * NG;
@@ -210,9 +199,15 @@ int32_t solver_create(const lbm3d_params* p, lbm3d_solver** out)
     h->md = make_model(p);
     h->mf = model_to_float(h->md);
     for (int f = 0; f < 6; f++) h->bc.kind[f] = p->bc[f];
+    h->upwind2 = (p->flags & LBM3D_UPWIND2) != 0;
     h->tile = default_tile(h->mode, h->g);
     TileCfg tuned;
     if (cached_tile(h->mode, h->g, h->bc, &tuned) && tile_supported(h->mode, h->g, tuned)) h->tile = tuned;
+    if (h->upwind2) {
+        // the variant runs in the untiled kernel
+        h->tile.by = 0;
+        h->tile.tz = 1;
+    }
     h->n = (int64_t)p->nx * p->ny * p->nz;
     const size_t fb = f_bytes(h->g, h->mode);
     h->nred = conserved_blocks(h->g);
@@ -251,7 +246,7 @@ int32_t solver_create(const lbm3d_params* p, lbm3d_solver** out)
 static hipError_t enqueue_one(lbm3d_solver* h, int cur, hipStream_t s)
 {
     hipError_t e = launch_step(h->mode, h->g, h->bc, h->tile, h->md, h->mf, h->p.inflow, h->f[cur], h->f[cur ^ 1],
-                               h->health, s);
+                               h->health, s, h->upwind2);
     if (e != hipSuccess) return e;
     const uint32_t rest = ghost_faces(h->g, h->bc, h->tile.by != 0);
     if (!rest) return hipSuccess;
@@ -365,6 +360,10 @@ int32_t lbm3d_init(lbm3d_t h, const double* rho, const double* ux, const double*
         if (!finite_pos(rho[k]) || !finite_pos(p[k])) return LBM3D_E_INVAL;
         if (!std::isfinite(ux[k]) || !std::isfinite(uy[k]) || !std::isfinite(uz[k])) return LBM3D_E_INVAL;
     }
+    if (h->p.flags & LBM3D_CHECK_STABILITY) {
+        const int32_t rc = admission(&h->p, rho, ux, uy, uz, p, nullptr);
+        if (rc) return rc;
+    }
     hipStream_t s = h->stream;
     const double* src[5] = {rho, ux, uy, uz, p};
     for (int c = 0; c < 5; c++)
@@ -420,7 +419,7 @@ int32_t lbm3d_step_profiled(lbm3d_t h, int64_t nsteps, double* total_ms, double*
         e = hipEventRecord(ev[2 * k], s);
         if (e == hipSuccess)
             e = launch_step(h->mode, h->g, h->bc, h->tile, h->md, h->mf, h->p.inflow, h->f[c], h->f[c ^ 1],
-                            h->health, s);
+                            h->health, s, h->upwind2);
         if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], s);
         const uint32_t rest = ghost_faces(h->g, h->bc, h->tile.by != 0);
         if (e == hipSuccess && rest)
@@ -453,7 +452,7 @@ int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz)
     TileCfg t;
     t.by = by;
     t.tz = tz;
-    if (!tile_supported(h->mode, h->g, t)) return LBM3D_E_INVAL;
+    if (!tile_supported(h->mode, h->g, t) || (h->upwind2 && by != 0)) return LBM3D_E_INVAL;
     HIPCHK(hipStreamSynchronize(h->stream));
     for (int k = 0; k < 2; k++)
         if (h->graph_exec[k]) {
@@ -521,6 +520,20 @@ int32_t lbm3d_status(lbm3d_t h, uint32_t* health, int64_t* steps_done)
     HIPCHK(hipStreamSynchronize(h->stream));
     if (health) *health = hw;
     if (steps_done) *steps_done = h->steps;
+    return LBM3D_OK;
+}
+
+int32_t lbm3d_poison_next(lbm3d_t h)
+{
+    if (!h) return LBM3D_E_INVAL;
+    if (!h->initialised) return LBM3D_E_STATE;
+    hipStream_t s = h->stream;
+    // all ones is a quiet NaN in both float and double
+    HIPCHK(hipMemsetAsync(h->f[h->cur ^ 1], 0xff, f_bytes(h->g, h->mode), s));
+    // the fixed-state layers are written once per buffer (at init), not by
+    // the steps: restore them
+    HIPCHK(launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, true, h->f[h->cur ^ 1], s, 0u));
+    HIPCHK(hipStreamSynchronize(s));
     return LBM3D_OK;
 }
 

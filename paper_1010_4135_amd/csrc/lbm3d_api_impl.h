@@ -22,6 +22,7 @@ struct lbm3d_solver {
     double* out5 = nullptr;
     uint32_t* health = nullptr;
     int nred = 0;
+    bool upwind2 = false;      // the second-order upwind variant (steps untiled)
     int cur = 0;               // buffer holding the current level
     int64_t steps = 0;
     bool initialised = false;
@@ -45,6 +46,11 @@ size_t f_bytes(const Grid& g, int precision);
 size_t footprint_of(const lbm3d_params* p);
 int32_t solver_create(const lbm3d_params* p, lbm3d_solver** out);
 int32_t solver_enqueue_steps(lbm3d_solver* h, int64_t nsteps);
+// Stability admission of an initial state (lbm3d_admit): E_UNSTABLE if the
+// von Neumann analysis at the state's extremes exceeds 1 + STABILITY_TOL.
+constexpr double STABILITY_TOL = 1e-3;
+int32_t admission(const lbm3d_params* p, const double* rho, const double* ux, const double* uy, const double* uz,
+                  const double* pr, double* worst);
 // autotuner results (lbm3d_tune.cpp): the tuned tile of a solve shape, and
 // the tuned batch tile depth of a precision (0 if not tuned)
 bool cached_tile(int mode, const Grid& g, const FaceBC& bc, TileCfg* out);

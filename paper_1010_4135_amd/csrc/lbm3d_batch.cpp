@@ -1,9 +1,11 @@
 // Batched stepping: many solves of uneven size advanced by one persistent
-// launch per step over a packed tile list, with step runs replayed from a
+// launch per step over per-XCD tile lists, with step runs replayed from a
 // captured HIP graph.
 #include "lbm3d_batch.h"
 
 #include <algorithm>
+#include <climits>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <set>
@@ -17,13 +19,123 @@ static int32_t herr(hipError_t e)
 
 // Steps per captured graph of the batched step (even: parities 0,1,...).
 constexpr int BATCH_GRAPH_STEPS = 16;
-// z extent of a batch tile (build-time tuning knob)
-#ifndef LBM3D_BATCH_TZ
-#define LBM3D_BATCH_TZ 16
-#endif
+// Tile depth of the batched step before any tuning.
+constexpr int BATCH_DEFAULT_TZ = 32;
+// Planes a tile marches before its first update (the z prologue), counted
+// in the cost that balances the lists.
+constexpr double TILE_PROLOGUE_PLANES = 3.0;
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+static int device_cus()
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    return cus;
+}
+
+int32_t plan_tiles(const std::vector<Grid>& grids, int by, int tz, int cus, TilePlan& out)
+{
+    out = TilePlan();
+    if (by < 1 || tz < 1 || cus < 1) return LBM3D_E_INVAL;
+    // every member's tiles in natural order: z chunk, then row, then column
+    std::vector<BatchTile> all;
+    std::vector<double> tcost;
+    std::vector<size_t> mbegin(grids.size() + 1, 0);
+    for (size_t k = 0; k < grids.size(); k++) {
+        const Grid& g = grids[k];
+        mbegin[k] = all.size();
+        const int64_t ntx = (g.nx + TILE_X - 1) / TILE_X;
+        const int64_t nty = (g.ny + by - 1) / by;
+        const int64_t ntz = (g.nz + (int64_t)tz - 1) / tz;
+        if ((int64_t)all.size() + ntx * nty * ntz > (int64_t)INT32_MAX) return LBM3D_E_INVAL;
+        for (int64_t cz = 0; cz < ntz; cz++) {
+            const int z0 = (int)(cz * tz);
+            const int z1 = (int)std::min<int64_t>((int64_t)z0 + tz, g.nz);
+            for (int64_t ty = 0; ty < nty; ty++)
+                for (int64_t tx = 0; tx < ntx; tx++) {
+                    BatchTile t;
+                    t.solve = (int32_t)k;
+                    t.txi = (int32_t)tx;
+                    t.tyi = (int32_t)ty;
+                    t.z0 = z0;
+                    t.z1 = z1;
+                    all.push_back(t);
+                    tcost.push_back((z1 - z0) + TILE_PROLOGUE_PLANES);
+                }
+        }
+    }
+    mbegin[grids.size()] = all.size();
+    const int n = (int)all.size();
+    if (n == 0) return LBM3D_OK;
+    int nblocks = std::min(n, cus);
+    if (nblocks >= BATCH_MAX_LISTS) nblocks -= nblocks % BATCH_MAX_LISTS;
+    const int nlists = std::min(BATCH_MAX_LISTS, nblocks);
+    out.nblocks = nblocks;
+    out.nlists = nlists;
+
+    // contiguous pieces of each member, at most a quarter of a list's share each
+    struct Piece {
+        size_t begin, end;
+        double cost;
+    };
+    double total = 0.0;
+    for (double c : tcost) total += c;
+    const double piece_max = nlists > 1 ? 0.25 * total / nlists : total;
+    std::vector<Piece> pieces;
+    for (size_t k = 0; k < grids.size(); k++) {
+        double ck = 0.0;
+        for (size_t j = mbegin[k]; j < mbegin[k + 1]; j++) ck += tcost[j];
+        const int np = std::max(1, (int)std::ceil(ck / piece_max - 1e-9));
+        size_t b = mbegin[k];
+        double acc = 0.0;
+        for (int p = 0; p < np; p++) {
+            const double upto = ck * (p + 1) / np;
+            size_t e = b;
+            double pc = 0.0;
+            while (e < mbegin[k + 1] && (p == np - 1 || acc + tcost[e] <= upto + 1e-9 || e == b)) {
+                acc += tcost[e];
+                pc += tcost[e];
+                e++;
+            }
+            if (e > b) pieces.push_back(Piece{b, e, pc});
+            b = e;
+        }
+    }
+    // largest piece first onto the least-loaded list
+    std::stable_sort(pieces.begin(), pieces.end(), [](const Piece& a, const Piece& b) { return a.cost > b.cost; });
+    std::vector<std::vector<const Piece*>> lists((size_t)nlists);
+    for (const Piece& p : pieces) {
+        int best = 0;
+        for (int l = 1; l < nlists; l++)
+            if (out.cost[l] < out.cost[best]) best = l;
+        lists[(size_t)best].push_back(&p);
+        out.cost[best] += p.cost;
+    }
+    // each list: its pieces' tiles, deepest first (the order within a depth
+    // is kept, so neighbouring tiles run together)
+    out.tiles.reserve((size_t)n);
+    for (int l = 0; l < nlists; l++) {
+        out.queue.first[l] = (int32_t)out.tiles.size();
+        std::vector<BatchTile> lt;
+        for (const Piece* p : lists[(size_t)l])
+            for (size_t j = p->begin; j < p->end; j++) lt.push_back(all[j]);
+        std::stable_sort(lt.begin(), lt.end(),
+                         [](const BatchTile& a, const BatchTile& b) { return (a.z1 - a.z0) > (b.z1 - b.z0); });
+        out.tiles.insert(out.tiles.end(), lt.begin(), lt.end());
+    }
+    for (int l = nlists; l <= BATCH_MAX_LISTS; l++) out.queue.first[l] = (int32_t)out.tiles.size();
+    for (int l = 0; l < BATCH_MAX_LISTS; l++) out.queue.next[l] = 0;
+    return LBM3D_OK;
+}
 
 BatchPlan::~BatchPlan()
 {
+    if (last_stream_) (void)hipStreamSynchronize(last_stream_);
     release_graph();
     if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
     if (dmem_) (void)hipFree(dmem_);
@@ -31,30 +143,92 @@ BatchPlan::~BatchPlan()
 
 void BatchPlan::release_graph()
 {
+    // (callers have drained the stream the graph was launched on)
     if (graph_) (void)hipGraphExecDestroy(graph_);
     graph_ = nullptr;
 }
 
-int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t s, int tz)
+static int plan_depth(int mode, int tz)
 {
+    int t = tz > 0 ? tz : batch_tile_depth(mode);
+    return t > 0 ? t : BATCH_DEFAULT_TZ;
+}
+
+// layer jobs of the members (faces the tiles leave to memory)
+static void layer_jobs(const std::vector<lbm3d_solver*>& members, std::vector<uint32_t>& rest,
+                       std::vector<BatchLayerJob>& ljobs, std::vector<int32_t>& block_job, int& nlblocks)
+{
+    rest.assign(members.size(), 0u);
+    ljobs.clear();
+    nlblocks = 0;
+    for (size_t k = 0; k < members.size(); k++) {
+        const Grid& g = members[k]->g;
+        const uint32_t faces = ghost_faces(g, members[k]->bc, true);
+        rest[k] = faces;
+        if (!faces) continue;
+        int64_t lines = 0;
+        for (int face = 0; face < 6; face++) {
+            if (!((faces >> face) & 1)) continue;
+            const int axis = face >> 1;
+            lines += axis == 0 ? (int64_t)g.ny * g.nz : axis == 1 ? (int64_t)g.nx * g.nz : (int64_t)g.nx * g.ny;
+        }
+        BatchLayerJob jb;
+        jb.solve = (int32_t)k;
+        jb.faces = faces;
+        jb.first = nlblocks;
+        ljobs.push_back(jb);
+        nlblocks += (int)((lines + 63) / 64);
+    }
+    block_job.assign((size_t)nlblocks, 0);
+    for (size_t j = 0; j < ljobs.size(); j++) {
+        const int end = j + 1 < ljobs.size() ? ljobs[j + 1].first : nlblocks;
+        for (int b = ljobs[j].first; b < end; b++) block_job[(size_t)b] = (int32_t)j;
+    }
+}
+
+static size_t tables_need(size_t nmembers, size_t ntiles, size_t nljobs, size_t nlblocks)
+{
+    return align256(nmembers * sizeof(BatchSolve)) + align256(ntiles * sizeof(BatchTile)) +
+           align256(sizeof(BatchQueue)) + align256(nljobs * sizeof(BatchLayerJob)) +
+           align256(nlblocks * sizeof(int32_t)) + nmembers * sizeof(uint32_t) + 256;
+}
+
+size_t BatchPlan::table_bytes(const std::vector<lbm3d_solver*>& members, int tz)
+{
+    if (members.empty()) return 0;
+    const int mode = members[0]->mode;
+    const int by = mode == LBM3D_FP64 ? 4 : 8;
+    std::vector<Grid> grids;
+    for (lbm3d_solver* h : members) grids.push_back(h->g);
+    TilePlan p;
+    if (plan_tiles(grids, by, plan_depth(mode, tz), device_cus(), p) != LBM3D_OK) return (size_t)-1;
+    std::vector<uint32_t> rest;
+    std::vector<BatchLayerJob> lj;
+    std::vector<int32_t> bj;
+    int nlb = 0;
+    layer_jobs(members, rest, lj, bj, nlb);
+    return tables_need(members.size(), p.tiles.size(), lj.size(), (size_t)nlb);
+}
+
+int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t s, int tz, void* dev, size_t cap)
+{
+    // work still queued may read the old tables or replay the old graph
+    if (last_stream_ && hipStreamSynchronize(last_stream_) != hipSuccess) return LBM3D_E_DEVICE;
+    last_stream_ = nullptr;
     release_graph();
     members_ = members;
-    ntiles_ = 0;
+    plan_ = TilePlan();
     parity_ = 0;
     if (members.empty()) return LBM3D_OK;
     mode_ = members[0]->mode;
     by_ = mode_ == LBM3D_FP64 ? 4 : 8;
-    // tile depth: the caller's, else the tuned one, else the build default
-    tz_ = tz > 0 ? tz : batch_tile_depth(mode_);
-    if (tz_ <= 0) tz_ = LBM3D_BATCH_TZ;
+    tz_ = plan_depth(mode_, tz);
+    std::vector<Grid> grids;
+    for (lbm3d_solver* h : members) grids.push_back(h->g);
+    int32_t rc = plan_tiles(grids, by_, tz_, device_cus(), plan_);
+    if (rc) return rc;
 
-    // packed tile list: each solve's tiles in (z chunk, y, x) order, split
-    // into eight contiguous runs interleaved so that run c lands on XCD c
-    // (workgroup b runs tiles b, b + G, ... with G a multiple of 8)
-    std::vector<BatchTile> order;
     std::vector<BatchSolve> table(members.size());
-    ghost_rest_.assign(members.size(), 0u);
-    cur0_.assign(members.size(), 0);
     for (size_t k = 0; k < members.size(); k++) {
         lbm3d_solver* h = members[k];
         BatchSolve& d = table[k];
@@ -68,118 +242,91 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
         d.health = h->health;
         d.md = h->md;
         d.mf = h->mf;
-        ghost_rest_[k] = ghost_faces(h->g, h->bc, true);
-        cur0_[k] = h->cur;
-        const int ntx = (h->g.nx + TILE_X - 1) / TILE_X;
-        const int nty = (h->g.ny + by_ - 1) / by_;
-        for (int z0 = 0; z0 < h->g.nz; z0 += tz_)
-            for (int ty = 0; ty < nty; ty++)
-                for (int tx = 0; tx < ntx; tx++) {
-                    BatchTile t;
-                    t.solve = (int32_t)k;
-                    t.txi = (int16_t)tx;
-                    t.tyi = (int16_t)ty;
-                    t.z0 = (int16_t)z0;
-                    t.z1 = (int16_t)std::min(z0 + tz_, h->g.nz);
-                    order.push_back(t);
-                }
     }
-    const int n = (int)order.size();
-    std::vector<BatchTile> tiles(n);
-    const int per = n / 8, rem = n % 8;
-    int pos = 0;
-    for (int c = 0; c < 8; c++) {
-        // slots c, c+8, c+16, ... (all < n) take run c of the natural order
-        const int cnt = per + (c < rem ? 1 : 0);
-        for (int j = 0; j < cnt; j++) tiles[8 * j + c] = order[pos + j];
-        pos += cnt;
-    }
-    ntiles_ = n;
-    // persistent grid: a multiple of 8 workgroups, about what the GPU holds
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-            cus = prop.multiProcessorCount;
-    }
-    // (one workgroup per CU is what the LDS of a tile leaves room for)
-    nblocks_ = std::min(n, cus);
-    if (nblocks_ >= 8) nblocks_ -= nblocks_ % 8;
-
-    // boundary layers left after each step: one launch over all members
     std::vector<BatchLayerJob> ljobs;
-    nlblocks_ = 0;
-    for (size_t k = 0; k < members.size(); k++) {
-        const uint32_t faces = ghost_rest_[k];
-        if (!faces) continue;
-        const Grid& g = members[k]->g;
-        int64_t lines = 0;
-        for (int face = 0; face < 6; face++) {
-            if (!((faces >> face) & 1)) continue;
-            const int axis = face >> 1;
-            lines += axis == 0 ? (int64_t)g.ny * g.nz : axis == 1 ? (int64_t)g.nx * g.nz : (int64_t)g.nx * g.ny;
-        }
-        BatchLayerJob jb;
-        jb.solve = (int32_t)k;
-        jb.faces = faces;
-        jb.first = nlblocks_;
-        ljobs.push_back(jb);
-        nlblocks_ += (int)((lines + 63) / 64);
-    }
+    std::vector<int32_t> block_job;
+    layer_jobs(members, ghost_rest_, ljobs, block_job, nlblocks_);
     nljobs_ = (int)ljobs.size();
-    std::vector<int32_t> block_job((size_t)nlblocks_);
-    for (int j = 0; j < nljobs_; j++) {
-        const int end = j + 1 < nljobs_ ? ljobs[j + 1].first : nlblocks_;
-        for (int b = ljobs[j].first; b < end; b++) block_job[(size_t)b] = j;
-    }
 
     const size_t sb = table.size() * sizeof(BatchSolve);
-    const size_t tb = (size_t)n * sizeof(BatchTile);
+    const size_t tb = plan_.tiles.size() * sizeof(BatchTile);
     const size_t lb = ljobs.size() * sizeof(BatchLayerJob);
     const size_t bb = block_job.size() * sizeof(int32_t);
-    const size_t need = ((sb + 255) / 256) * 256 + ((tb + 255) / 256) * 256 + ((lb + 255) / 256) * 256 + bb + 256;
-    if (need > dbytes_) {
-        if (dmem_) (void)hipFree(dmem_);
-        dmem_ = nullptr;
-        dbytes_ = 0;
-        hipError_t e = hipMalloc(&dmem_, need);
-        if (e != hipSuccess) return herr(e);
-        dbytes_ = need;
+    const size_t need = tables_need(table.size(), plan_.tiles.size(), ljobs.size(), block_job.size());
+    char* base = nullptr;
+    if (dev) {
+        if (need > cap) return LBM3D_E_NOMEM;
+        if (dmem_) {
+            (void)hipFree(dmem_);
+            dmem_ = nullptr;
+            dbytes_ = 0;
+        }
+        base = (char*)dev;
+    } else {
+        if (need > dbytes_) {
+            if (dmem_) (void)hipFree(dmem_);
+            dmem_ = nullptr;
+            dbytes_ = 0;
+            hipError_t e = hipMalloc(&dmem_, need);
+            if (e != hipSuccess) return herr(e);
+            dbytes_ = need;
+        }
+        base = (char*)dmem_;
     }
-    dsolves_ = (BatchSolve*)dmem_;
-    dtiles_ = (BatchTile*)((char*)dmem_ + ((sb + 255) / 256) * 256);
-    dlayers_ = (BatchLayerJob*)((char*)dtiles_ + ((tb + 255) / 256) * 256);
-    dblockjob_ = (int32_t*)((char*)dlayers_ + ((lb + 255) / 256) * 256);
+    dsolves_ = (BatchSolve*)base;
+    dtiles_ = (BatchTile*)(base + align256(sb));
+    dqueue_ = (BatchQueue*)((char*)dtiles_ + align256(tb));
+    dlayers_ = (BatchLayerJob*)((char*)dqueue_ + align256(sizeof(BatchQueue)));
+    dblockjob_ = (int32_t*)((char*)dlayers_ + align256(lb));
+    dhealth_ = (uint32_t*)((char*)dblockjob_ + align256(bb));
     hipError_t e = hipMemcpyAsync(dsolves_, table.data(), sb, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dtiles_, tiles.data(), tb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dtiles_, plan_.tiles.data(), tb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dqueue_, &plan_.queue, sizeof(BatchQueue), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && lb) e = hipMemcpyAsync(dlayers_, ljobs.data(), lb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && bb) e = hipMemcpyAsync(dblockjob_, block_job.data(), bb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables die at return
+    last_stream_ = nullptr;
     return herr(e);
 }
 
-hipError_t BatchPlan::launch_once(hipStream_t s) { return enqueue(0, s); }
+int32_t BatchPlan::health(std::vector<uint32_t>& out, hipStream_t s)
+{
+    out.assign(members_.size(), 0u);
+    if (members_.empty()) return LBM3D_OK;
+    hipError_t e = launch_gather_health(dsolves_, (int)members_.size(), dhealth_, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out.data(), dhealth_, out.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return herr(e);
+}
+
+hipError_t BatchPlan::launch_once(hipStream_t s)
+{
+    last_stream_ = s;
+    return enqueue(0, s);
+}
 
 hipError_t BatchPlan::enqueue(int parity, hipStream_t s)
 {
-    hipError_t e = launch_batch_step(mode_, by_, dsolves_, dtiles_, ntiles_, nblocks_, parity, s);
+    hipError_t e = launch_batch_step(mode_, by_, dsolves_, dtiles_, dqueue_, plan_.nlists, plan_.nblocks, parity, s);
     if (e != hipSuccess) return e;
     // boundary layers the tiles do not form themselves, all members at once
     return launch_batch_layers(mode_, dsolves_, dlayers_, dblockjob_, nlblocks_, parity, s);
 }
 
-int32_t BatchPlan::run(int64_t k, hipStream_t s)
+int32_t BatchPlan::run(int64_t k, hipStream_t s, bool graphs)
 {
     if (members_.empty() || k <= 0) return LBM3D_OK;
+    last_stream_ = s;
     int64_t left = k;
     // align to an even parity so the captured graph (parities 0,1,...) applies
-    if (parity_ & 1) {
+    if (graphs && (parity_ & 1)) {
         hipError_t e = enqueue(1, s);
         if (e != hipSuccess) return herr(e);
         parity_ ^= 1;
         left--;
     }
-    while (left >= BATCH_GRAPH_STEPS) {
+    while (graphs && left >= BATCH_GRAPH_STEPS) {
         if (!graph_) {
             if (!capture_stream_) {
                 hipError_t e = hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking);
@@ -222,27 +369,28 @@ int32_t BatchPlan::run(int64_t k, hipStream_t s)
     return LBM3D_OK;
 }
 
-}  // namespace lbm3d
-
-// ------------------------------------------------------------------- C ABI --
-using namespace lbm3d;
-
-extern "C" int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* nsteps)
+// Checks shared by the batched entry points: non-null distinct handles,
+// initialised, one precision, within the tiled kernels' addressing.
+int32_t check_batch(lbm3d_t* hs, int32_t count)
 {
-    if (!hs || !nsteps || count < 1) return LBM3D_E_INVAL;
+    if (!hs || count < 1) return LBM3D_E_INVAL;
     std::set<lbm3d_t> seen;
     for (int32_t k = 0; k < count; k++) {
-        if (!hs[k] || nsteps[k] < 0 || !seen.insert(hs[k]).second) return LBM3D_E_INVAL;
+        if (!hs[k] || !seen.insert(hs[k]).second) return LBM3D_E_INVAL;
         if (!hs[k]->initialised) return LBM3D_E_STATE;
         if (hs[k]->mode != hs[0]->mode) return LBM3D_E_INVAL;
-        if (!lbm3d::tiled_fits(hs[k]->mode, hs[k]->g)) return LBM3D_E_INVAL;
+        if (!tiled_fits(hs[k]->mode, hs[k]->g)) return LBM3D_E_INVAL;
+        if (hs[k]->upwind2) return LBM3D_E_INVAL;  // the batched kernel is NND only
     }
-    hipStream_t s = hs[0]->stream;
-    // work already queued on the other solves' streams precedes the batch
-    for (int32_t k = 1; k < count; k++)
-        if (hs[k]->stream != s && hipStreamSynchronize(hs[k]->stream) != hipSuccess) return LBM3D_E_DEVICE;
+    return LBM3D_OK;
+}
+
+// Steps of a batch whose members need different step counts: runs of the
+// common count with the members that still have steps to do.
+int32_t batch_advance(lbm3d_t* hs, int32_t count, const int64_t* nsteps, hipStream_t s, BatchPlan& plan,
+                      void* dev, size_t cap, bool graphs)
+{
     std::vector<int64_t> left(nsteps, nsteps + count);
-    BatchPlan plan;
     for (;;) {
         std::vector<lbm3d_solver*> active;
         int64_t k = 0;
@@ -252,12 +400,75 @@ extern "C" int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* n
                 k = (k == 0) ? left[j] : std::min(k, left[j]);
             }
         if (active.empty()) break;
-        int32_t rc = plan.build(active, s);
+        int32_t rc = plan.build(active, s, 0, dev, cap);
         if (rc) return rc;
-        rc = plan.run(k, s);
+        rc = plan.run(k, s, graphs);
         if (rc) return rc;
         for (int32_t j = 0; j < count; j++)
             if (left[j] > 0) left[j] -= k;
     }
     return hipStreamSynchronize(s) == hipSuccess ? LBM3D_OK : LBM3D_E_DEVICE;
+}
+
+}  // namespace lbm3d
+
+// ------------------------------------------------------------------- C ABI --
+using namespace lbm3d;
+
+extern "C" int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* nsteps)
+{
+    int32_t rc = check_batch(hs, count);
+    if (rc) return rc;
+    if (!nsteps) return LBM3D_E_INVAL;
+    for (int32_t k = 0; k < count; k++)
+        if (nsteps[k] < 0) return LBM3D_E_INVAL;
+    hipStream_t s = hs[0]->stream;
+    // work already queued on the other solves' streams precedes the batch
+    for (int32_t k = 1; k < count; k++)
+        if (hs[k]->stream != s && hipStreamSynchronize(hs[k]->stream) != hipSuccess) return LBM3D_E_DEVICE;
+    BatchPlan plan;
+    return batch_advance(hs, count, nsteps, s, plan, nullptr, 0, true);
+}
+
+extern "C" int32_t lbm3d_batch_plan(const lbm3d_params* ps, int32_t count, int32_t tz, int32_t cus,
+                                    int32_t* ntiles, int32_t* nlists, int32_t* nblocks, int32_t* tiles,
+                                    int64_t cap, int32_t* list_first)
+{
+    if (!ps || count < 1 || cus < 1) return LBM3D_E_INVAL;
+    std::vector<Grid> grids;
+    for (int32_t k = 0; k < count; k++) {
+        int32_t rc = validate(&ps[k]);
+        if (rc) return rc;
+        if (ps[k].precision != ps[0].precision || (ps[k].flags & LBM3D_UPWIND2)) return LBM3D_E_INVAL;
+        const Grid g = make_grid(&ps[k]);
+        if (!tiled_fits(ps[k].precision, g)) return LBM3D_E_INVAL;
+        grids.push_back(g);
+    }
+    const int mode = ps[0].precision;
+    const int by = mode == LBM3D_FP64 ? 4 : 8;
+    TilePlan p;
+    int32_t rc = plan_tiles(grids, by, plan_depth(mode, tz), cus, p);
+    if (rc) return rc;
+    const int64_t n = (int64_t)p.tiles.size();
+    if (ntiles) *ntiles = (int32_t)n;
+    if (nlists) *nlists = p.nlists;
+    if (nblocks) *nblocks = p.nblocks;
+    if (list_first)
+        for (int l = 0; l <= BATCH_MAX_LISTS; l++) list_first[l] = p.queue.first[l];
+    if (tiles) {
+        if (cap < n) return LBM3D_E_NOMEM;
+        for (int64_t j = 0; j < n; j++) {
+            const BatchTile& t = p.tiles[(size_t)j];
+            const Grid& g = grids[(size_t)t.solve];
+            int32_t* o = tiles + 7 * j;
+            o[0] = t.solve;
+            o[1] = t.txi * TILE_X;
+            o[2] = std::min(o[1] + TILE_X, g.nx);
+            o[3] = t.tyi * by;
+            o[4] = std::min(o[3] + by, g.ny);
+            o[5] = t.z0;
+            o[6] = t.z1;
+        }
+    }
+    return LBM3D_OK;
 }

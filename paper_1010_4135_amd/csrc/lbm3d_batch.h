@@ -7,9 +7,26 @@
 
 namespace lbm3d {
 
+// Work plan of a batched step, computed on the host: the tiles of every
+// member split into per-XCD lists (see plan_tiles).
+struct TilePlan {
+    std::vector<BatchTile> tiles;  // list 0's tiles, then list 1's, ...
+    BatchQueue queue{};            // list boundaries; counters zero
+    int nlists = 0;                // lists (one per XCD, fewer for tiny batches)
+    int nblocks = 0;               // persistent workgroups, a multiple of nlists
+    double cost[BATCH_MAX_LISTS] = {};  // planes marched per list (balance)
+};
+
+// Tiles of 64 x `by` x `tz` nodes (tz >= nz: whole columns) over the grids,
+// for `cus` compute units.  Each member's tiles are cut into contiguous
+// pieces (row slabs, which share their halo rows through one L2), the pieces
+// are dealt to the lists largest first onto the least-loaded list, and each
+// list runs its deepest tiles first.  Host only.
+int32_t plan_tiles(const std::vector<Grid>& grids, int by, int tz, int cus, TilePlan& out);
+
 // A fixed set of solves (one precision) advanced together: a device table
-// of the solves, a packed tile list over all of them and a persistent
-// launch per step; runs of steps are replayed from a captured graph.
+// of the solves, the tile lists over all of them and a persistent launch
+// per step; runs of steps are replayed from a captured graph.
 class BatchPlan {
 public:
     BatchPlan() = default;
@@ -20,35 +37,59 @@ public:
     // (Re)build for `members` (all initialised, same precision); each
     // member's current buffer is taken as parity 0.  Enqueued on `s`.
     // `tz` > 0 sets the tile depth, else the tuned or default one is used.
-    int32_t build(const std::vector<lbm3d_solver*>& members, hipStream_t s, int tz = 0);
+    // The device tables go into a buffer the plan allocates, or, with
+    // `dev` != nullptr, into the caller's `cap` bytes at `dev` (then nothing
+    // is allocated and E_NOMEM is returned if they do not fit).
+    int32_t build(const std::vector<lbm3d_solver*>& members, hipStream_t s, int tz = 0,
+                  void* dev = nullptr, size_t cap = 0);
+    // Device bytes the tables of `members` need at tile depth tz (0: the
+    // tuned or default depth).
+    static size_t table_bytes(const std::vector<lbm3d_solver*>& members, int tz = 0);
     // One step of every member from the build-time buffers into the other
     // ones, without advancing anything (for timing: repeated launches
     // recompute the same next level).
     hipError_t launch_once(hipStream_t s);
     // Enqueue k steps of every member on `s` and update the members'
-    // buffer parity and step counters.
-    int32_t run(int64_t k, hipStream_t s);
-    int ntiles() const { return ntiles_; }
+    // buffer parity and step counters; `graphs` = false launches every step
+    // directly (no graph is instantiated).
+    int32_t run(int64_t k, hipStream_t s, bool graphs = true);
+    // Health words of the members (in build order) after the work queued
+    // on `s`; waits for `s`.
+    int32_t health(std::vector<uint32_t>& out, hipStream_t s);
+    int ntiles() const { return (int)plan_.tiles.size(); }
     int by() const { return by_; }
+    int tz() const { return tz_; }
 
 private:
     hipError_t enqueue(int parity, hipStream_t s);
     void release_graph();
 
     std::vector<lbm3d_solver*> members_;
-    int mode_ = 0, by_ = 8, tz_ = 8, ntiles_ = 0, nblocks_ = 0;
-    void* dmem_ = nullptr;  // solve table + tile list
+    int mode_ = 0, by_ = 8, tz_ = 8;
+    TilePlan plan_;
+    void* dmem_ = nullptr;  // tables allocated by the plan (nullptr with a caller's buffer)
     size_t dbytes_ = 0;
     BatchSolve* dsolves_ = nullptr;
     BatchTile* dtiles_ = nullptr;
+    BatchQueue* dqueue_ = nullptr;
     BatchLayerJob* dlayers_ = nullptr;  // boundary-layer jobs (sorted by first workgroup)
     int32_t* dblockjob_ = nullptr;      // job of each boundary-layer workgroup
+    uint32_t* dhealth_ = nullptr;       // gathered health words, one per member
     int nljobs_ = 0, nlblocks_ = 0;
     std::vector<uint32_t> ghost_rest_;  // per member: faces left to the boundary-layer launch
-    std::vector<int> cur0_;             // per member: current buffer at build()
     hipGraphExec_t graph_ = nullptr;
     hipStream_t capture_stream_ = nullptr;
+    hipStream_t last_stream_ = nullptr;  // stream of the last enqueued work (drained before teardown)
     int parity_ = 0;  // parity of the next step relative to build()
 };
+
+// Checks shared by the batched entry points (E_INVAL / E_STATE).
+int32_t check_batch(lbm3d_t* hs, int32_t count);
+// Advance members by their own step counts (runs of the common count with
+// the members that still have steps to do), then wait for `s`.  Tables go
+// into `dev` (cap bytes) when given; `graphs` = false launches every step
+// directly.
+int32_t batch_advance(lbm3d_t* hs, int32_t count, const int64_t* nsteps, hipStream_t s, BatchPlan& plan,
+                      void* dev, size_t cap, bool graphs);
 
 }  // namespace lbm3d

@@ -16,7 +16,7 @@ namespace lbm3d {
 // This one-node-per-thread kernel and the tiled one evaluate the same
 // operations per node (node_update and the NND helpers), so they agree
 // bitwise.
-template <int I, typename S, typename C>
+template <int I, bool U2, typename S, typename C>
 __device__ __forceinline__ void update_one(const S* __restrict__ fi, S* __restrict__ fo, int64_t site,
                                            const int64_t (&xo)[4], int64_t sy, int64_t sz, C f0, C feq,
                                            const Model<C>& m)
@@ -36,12 +36,12 @@ __device__ __forceinline__ void update_one(const S* __restrict__ fi, S* __restri
         if (SG[a] > 0) {
             const C fm2 = nb(a, -2), fm1 = nb(a, -1), fp1 = nb(a, 1);
             const C e0 = f0 - fm1, e1 = fp1 - f0;
-            D[a] = nnd_pos(fm1 - fm2, e0, e1);
+            D[a] = U2 ? up2_pos(fm1 - fm2, e0) : nnd_pos(fm1 - fm2, e0, e1);
             L[a] = e1 - e0;
         } else if (SG[a] < 0) {
             const C fm1 = nb(a, -1), fp1 = nb(a, 1), fp2 = nb(a, 2);
             const C e0 = f0 - fm1, e1 = fp1 - f0;
-            D[a] = nnd_neg(e0, e1, fp2 - fp1);
+            D[a] = U2 ? up2_neg(e1, fp2 - fp1) : nnd_neg(e0, e1, fp2 - fp1);
             L[a] = e1 - e0;
         } else if (G <= 1) {
             L[a] = nb(a, -1) + nb(a, 1);
@@ -50,14 +50,14 @@ __device__ __forceinline__ void update_one(const S* __restrict__ fi, S* __restri
     fo[site] = static_cast<S>(node_update<I, C>(f0, feq, D[0], D[1], D[2], L[0], L[1], L[2], m));
 }
 
-template <typename S, typename C, int I = 0>
+template <bool U2, typename S, typename C, int I = 0>
 __device__ __forceinline__ void update_all(const S* __restrict__ f, S* __restrict__ fn, int64_t site,
                                            const int64_t (&xo)[4], int64_t sv, int64_t sy, int64_t sz,
                                            const C (&fc)[NV], const C (&feq)[NV], const Model<C>& m)
 {
     if constexpr (I < NV) {
-        update_one<I, S, C>(f + I * sv, fn + I * sv, site, xo, sy, sz, fc[I], feq[I], m);
-        update_all<S, C, I + 1>(f, fn, site, xo, sv, sy, sz, fc, feq, m);
+        update_one<I, U2, S, C>(f + I * sv, fn + I * sv, site, xo, sy, sz, fc[I], feq[I], m);
+        update_all<U2, S, C, I + 1>(f, fn, site, xo, sv, sy, sz, fc, feq, m);
     }
 }
 
@@ -77,7 +77,8 @@ __device__ __forceinline__ void x_offsets(const Grid& g, int x, int y, int z, in
     }
 }
 
-template <int MODE>
+// U2: the second-order upwind variant in place of NND (untiled only).
+template <int MODE, bool U2>
 __global__ void __launch_bounds__(TX * TY)
 k_step(Grid g, Model<double> md, Model<float> mf, const typename Types<MODE>::S* __restrict__ f,
        typename Types<MODE>::S* __restrict__ fn, uint32_t* __restrict__ health)
@@ -102,48 +103,22 @@ k_step(Grid g, Model<double> md, Model<float> mf, const typename Types<MODE>::S*
     equilibrium<C, M>(q, mm, mc, feq);
     int64_t xo[4];
     x_offsets(g, x, y, z, site, xo);
-    update_all<S, C>(f, fn, site, xo, g.sv, g.sy, g.sz, fc, feq, mc);
+    update_all<U2, S, C>(f, fn, site, xo, g.sv, g.sy, g.sz, fc, feq, mc);
 }
 
 // Tiled fused step: one workgroup per 64 x BY x TZ tile (see lbm3d_tile.h).
-// LBM3D_WAVES_PER_EU (build-time tuning knob): register budget of the tiled
-// kernel as wavefronts per SIMD (0 = compiler's choice).
-#ifndef LBM3D_WAVES_PER_EU
-#define LBM3D_WAVES_PER_EU 0
-#endif
-#if LBM3D_WAVES_PER_EU > 0
-#define LBM3D_TILED_ATTR __attribute__((amdgpu_waves_per_eu(LBM3D_WAVES_PER_EU)))
-#else
-#define LBM3D_TILED_ATTR
-#endif
-// LBM3D_BATCH_VK: the batched step's tiles hold the FP64 model constants in
-// vector registers too (1) or leave them to the scalar file (0).
-#ifndef LBM3D_BATCH_VK
-#define LBM3D_BATCH_VK 1
-#endif
-// LBM3D_BATCH_KEEP: the batched step keeps each tile's solve parameters in
-// registers (1) or lets the compiler re-load them from the table (0).
-#ifndef LBM3D_BATCH_KEEP
-#define LBM3D_BATCH_KEEP 1
-#endif
 
 template <int MODE, int BY>
-__global__ void __launch_bounds__(TILE_X * BY) LBM3D_TILED_ATTR
+__global__ void __launch_bounds__(TILE_X * BY)
 k_step_tiled(StepArgs<MODE> A, Model<double> md, Model<float> mf, int ntx, int nty, int tz)
 {
     __shared__ TilePlane<BY, typename Types<MODE>::S> P[2];
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-#if LBM3D_TILE_ORDER_X
+    // tiles numbered x fastest, then y, then the z chunk
     const int txi = t % ntx;
     const int r = t / ntx;
     const int tyi = r % nty;
     const int tzi = r / nty;
-#else
-    const int tyi = t % nty;
-    const int r = t / nty;
-    const int txi = r % ntx;
-    const int tzi = r / ntx;
-#endif
     const int z0 = tzi * tz;
     const int z1 = min(z0 + tz, A.g.nz);
     step_tile<MODE, BY>(A, md, mf, txi * TILE_X, tyi * BY, z0, z1, P);
@@ -171,13 +146,33 @@ __device__ __forceinline__ void keep_model(Model<T>& m)
 }
 
 template <int MODE, int BY>
-__global__ void __launch_bounds__(TILE_X * BY) LBM3D_TILED_ATTR
-k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict__ tiles, int ntiles, int parity)
+__global__ void __launch_bounds__(TILE_X * BY)
+k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict__ tiles, BatchQueue* queue,
+             int nlists, int parity)
 {
     using S = typename Types<MODE>::S;
     __shared__ TilePlane<BY, S> P[2];
-    for (int t = (int)blockIdx.x; t < ntiles; t += (int)gridDim.x) {
-        const BatchTile tile = tiles[t];
+    __shared__ int s_k;
+    // workgroup b works on list b mod nlists (dispatch places workgroup b on
+    // XCD b mod 8, so a list's tiles share one L2); the `per` workgroups of a
+    // list take its tiles in order from the list's counter
+    const int list = (int)blockIdx.x % nlists;
+    const int per = (int)gridDim.x / nlists;
+    const int first = queue->first[list];
+    const int cnt = queue->first[list + 1] - first;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int k = (int)atomicAdd(&queue->next[list], 1u);
+            // every workgroup makes exactly one grab past the end, so the
+            // one that draws cnt + per - 1 is the last to touch the counter:
+            // it leaves it at zero for the next launch
+            if (k == cnt + per - 1) atomicExch(&queue->next[list], 0u);
+            s_k = k;
+        }
+        __syncthreads();
+        const int k = s_k;
+        if (k >= cnt) break;
+        const BatchTile tile = tiles[first + k];
         const BatchSolve& d = solves[tile.solve];
         StepArgs<MODE> A;
         A.g = d.g;
@@ -187,20 +182,26 @@ k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict_
         A.fn = (S*)d.f[cur ^ 1];
         A.health = d.health;
 #pragma unroll
-        for (int k = 0; k < 10; k++) A.xin[k / 5][k % 5] = d.xin[k / 5][k % 5];
+        for (int j = 0; j < 10; j++) A.xin[j / 5][j % 5] = d.xin[j / 5][j % 5];
         Model<double> md = d.md;
         Model<float> mf = d.mf;
-#if LBM3D_BATCH_KEEP
         // the tile's solve is read once per tile: without this the compiler
         // re-loads its constants and strides from the table in every plane,
         // each a scalar-memory round trip the plane then waits for
         keep(A.g.sy); keep(A.g.sz); keep(A.g.sv); keep(A.g.org); keep(A.g.sink); keep(A.g.xg);
         keep(A.f); keep(A.fn);
         keep_model(mf);
-#endif
-        step_tile<MODE, BY, LBM3D_BATCH_VK>(A, md, mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
-        lds_barrier();  // the plane buffers are reused by the next tile
+        step_tile<MODE, BY, true>(A, md, mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
+        lds_barrier();  // the plane buffers (and s_k) are reused by the next tile
     }
+}
+
+// Health words of the members of a batch, gathered into one array.
+__global__ void __launch_bounds__(64)
+k_gather_health(const BatchSolve* __restrict__ solves, int n, uint32_t* __restrict__ out)
+{
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k < n) out[k] = *solves[k].health;
 }
 
 // ------------------------------------------------------- initial state ----
@@ -505,8 +506,8 @@ uint32_t ghost_faces(const Grid& g, const FaceBC& bc, bool tiled)
     for (int face = 0; face < 6; face++) {
         const int kind = bc.kind[face], axis = face >> 1;
         if (kind == BC_INFLOW) continue;
-        if (tiled && LBM3D_X_IN_TILE && axis == 0 && g.nx % TILE_X == 0) continue;
-        if (tiled && LBM3D_WRAP && kind == BC_PERIODIC) continue;
+        if (tiled && axis == 0 && g.nx % TILE_X == 0) continue;
+        if (tiled && kind == BC_PERIODIC) continue;
         m |= 1u << face;
     }
     return m;
@@ -546,8 +547,9 @@ static void launch_tiled(const Grid& g, const FaceBC& bc, int tz, const Model<do
 
 hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg& tc, const Model<double>& md,
                        const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
-                       uint32_t* health, hipStream_t s)
+                       uint32_t* health, hipStream_t s, bool upwind2)
 {
+    if (upwind2 && tc.by != 0) return hipErrorInvalidValue;
     if (tc.by != 0) {
         switch (tc.by) {
         case 2: LBM3D_DISPATCH(mode, launch_tiled<MD, 2>(g, bc, tc.tz, md, mf, inflow, f, fn, health, s)); break;
@@ -561,7 +563,11 @@ hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg&
         return hipGetLastError();
     }
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, g.nz);
-    LBM3D_DISPATCH(mode, k_step<MD><<<grid, dim3(TX, TY), 0, s>>>(g, md, mf, (const typename Types<MD>::S*)f, (typename Types<MD>::S*)fn, health));
+    if (upwind2) {
+        LBM3D_DISPATCH(mode, k_step<MD, true><<<grid, dim3(TX, TY), 0, s>>>(g, md, mf, (const typename Types<MD>::S*)f, (typename Types<MD>::S*)fn, health));
+    } else {
+        LBM3D_DISPATCH(mode, k_step<MD, false><<<grid, dim3(TX, TY), 0, s>>>(g, md, mf, (const typename Types<MD>::S*)f, (typename Types<MD>::S*)fn, health));
+    }
     return hipGetLastError();
 }
 
@@ -641,6 +647,13 @@ hipError_t launch_pack(int mode, const Grid& g, const void* f, void* dense, bool
     return hipGetLastError();
 }
 
+hipError_t launch_gather_health(const BatchSolve* solves, int n, uint32_t* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_gather_health<<<dim3(blocks_for(n, 64)), dim3(64), 0, s>>>(solves, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLayerJob* jobs, const int32_t* block_job,
                                int nblocks, int parity, hipStream_t s)
 {
@@ -649,19 +662,19 @@ hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLa
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles, int ntiles,
-                             int nblocks, int parity, hipStream_t s)
+hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles,
+                             BatchQueue* queue, int nlists, int nblocks, int parity, hipStream_t s)
 {
-    if (ntiles <= 0) return hipSuccess;
-    const dim3 grid((unsigned)std::max(1, std::min(nblocks, ntiles)));
+    if (nblocks <= 0 || nlists <= 0 || nlists > BATCH_MAX_LISTS || nblocks % nlists) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nblocks);
     switch (by) {
-    case 2: LBM3D_DISPATCH(mode, k_batch_step<MD, 2><<<grid, dim3(TILE_X * 2), 0, s>>>(solves, tiles, ntiles, parity)); break;
+    case 2: LBM3D_DISPATCH(mode, k_batch_step<MD, 2><<<grid, dim3(TILE_X * 2), 0, s>>>(solves, tiles, queue, nlists, parity)); break;
     case 8:
         if (mode == MODE_FP64) return hipErrorInvalidValue;
-        if (mode == MODE_FP32) k_batch_step<MODE_FP32, 8><<<grid, dim3(TILE_X * 8), 0, s>>>(solves, tiles, ntiles, parity);
-        else k_batch_step<MODE_FP32_T64, 8><<<grid, dim3(TILE_X * 8), 0, s>>>(solves, tiles, ntiles, parity);
+        if (mode == MODE_FP32) k_batch_step<MODE_FP32, 8><<<grid, dim3(TILE_X * 8), 0, s>>>(solves, tiles, queue, nlists, parity);
+        else k_batch_step<MODE_FP32_T64, 8><<<grid, dim3(TILE_X * 8), 0, s>>>(solves, tiles, queue, nlists, parity);
         break;
-    case 4: LBM3D_DISPATCH(mode, k_batch_step<MD, 4><<<grid, dim3(TILE_X * 4), 0, s>>>(solves, tiles, ntiles, parity)); break;
+    case 4: LBM3D_DISPATCH(mode, k_batch_step<MD, 4><<<grid, dim3(TILE_X * 4), 0, s>>>(solves, tiles, queue, nlists, parity)); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

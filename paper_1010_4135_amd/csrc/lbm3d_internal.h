@@ -56,10 +56,20 @@ struct Device;  // per-solve device pointers, defined in lbm3d_api.cpp
 enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_FP32_T64 = 2 };
 
 // One tile of the batched step: a 64 x BY x (z1 - z0) box of one solve.
+// (32-bit fields: a solve may have up to 2^20 rows and 65535 planes.)
 struct BatchTile {
     int32_t solve;        // index into the solve table
-    int16_t txi, tyi;     // tile column (x0 = 64 txi, y0 = BY tyi)
-    int16_t z0, z1;       // z range
+    int32_t txi, tyi;     // tile column (x0 = 64 txi, y0 = BY tyi)
+    int32_t z0, z1;       // z range
+};
+
+// Work lists of the batched step: the tiles are split into `nlists` lists
+// (one per XCD), list l holding tiles [first[l], first[l + 1]); the
+// workgroups of a list take its tiles in order from a counter.
+constexpr int BATCH_MAX_LISTS = 8;
+struct BatchQueue {
+    int32_t first[BATCH_MAX_LISTS + 1];
+    uint32_t next[BATCH_MAX_LISTS];  // zero between launches
 };
 
 // Per-solve entry of the batched step (device memory, read uniformly).
@@ -101,9 +111,10 @@ bool tiled_fits(int mode, const Grid& g);
 // (nx a multiple of 64) and wrap periodic faces, so with `tiled` those
 // faces need no layers in memory.
 uint32_t ghost_faces(const Grid& g, const FaceBC& bc, bool tiled);
+// upwind2: the second-order upwind variant (untiled kernel only: tc.by == 0)
 hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg& tc, const Model<double>& md,
                        const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
-                       uint32_t* health, hipStream_t s);
+                       uint32_t* health, hipStream_t s, bool upwind2 = false);
 // (rho, ux, uy, uz, T) of the two x faces' fixed states, from the ABI's
 // (rho, ux, uy, uz, p)
 void x_fixed_states(const double (*inflow)[5], double (&xin)[2][5]);
@@ -122,35 +133,22 @@ hipError_t launch_pack(int mode, const Grid& g, const void* f, void* dense, bool
 // Boundary layers of the members of a batch after a step (one launch).
 hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLayerJob* jobs, const int32_t* block_job,
                                int nblocks, int parity, hipStream_t s);
-hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles, int ntiles,
-                             int nblocks, int parity, hipStream_t s);
+// out[k] = the health word of member k (n members).
+hipError_t launch_gather_health(const BatchSolve* solves, int n, uint32_t* out, hipStream_t s);
+// One step of every member: `nblocks` persistent workgroups (a multiple of
+// `nlists`); workgroup b works on list b mod nlists.
+hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles,
+                             BatchQueue* queue, int nlists, int nblocks, int parity, hipStream_t s);
 
 // block shape of the untiled step kernel; x extent of a tile of the tiled one
 constexpr int TX = 64, TY = 4;
 constexpr int TILE_X = 64;
 
-// Build-time layout and tiling knobs:
-//  - LBM3D_X_IN_TILE: tiles form the x boundary layers themselves when
-//    64-wide tiles cover x exactly (1), or read them from memory (0);
-//  - LBM3D_WRAP: periodic faces wrap inside the tiles (1) or are read
-//    from memory (0);
-//  - LBM3D_DENSE_X: rows of such grids hold the interior only (mx = nx) and
-//    the x layers live in a block of their own (1), or rows are padded by a
-//    cache line holding the layers (0).  Streaming dense rows reaches about
-//    8 TB/s on a 256-wide grid against about 6 TB/s with padded rows.
-#ifndef LBM3D_X_IN_TILE
-#define LBM3D_X_IN_TILE 1
-#endif
-#ifndef LBM3D_WRAP
-#define LBM3D_WRAP 1
-#endif
-#ifndef LBM3D_DENSE_X
-#define LBM3D_DENSE_X 1
-#endif
-// Rows hold the interior only: the tiles never read x layers from memory.
-__host__ __device__ inline bool dense_rows(int nx)
-{
-    return LBM3D_DENSE_X && LBM3D_X_IN_TILE && LBM3D_WRAP && nx % TILE_X == 0;
-}
+// Rows hold the interior only (mx = nx) when 64-wide tiles cover x exactly:
+// the tiles then form the x boundary layers themselves and never read them
+// from memory, and the x layers live in a block of their own.  Streaming
+// dense rows reaches about 8 TB/s on a 256-wide grid against about 6 TB/s
+// with rows padded by a cache line holding the layers.
+__host__ __device__ inline bool dense_rows(int nx) { return nx % TILE_X == 0; }
 
 }  // namespace lbm3d

@@ -127,14 +127,19 @@ __device__ __forceinline__ C feq_vel(int i, const EqCoef<C> c, const Model<C>& m
     return c.rho * w;
 }
 
-// f^eq of Eqs. (eq)/(e18) for all 15 velocities.
+// f^eq of Eqs. (eq)/(e18) for all 15 velocities, evaluated in the moment
+// type M and rounded once to the bulk type C.  (In the FP32_T64 mode the
+// polynomial A + B s + D s^2 cancels strongly at high Mach number -- by a
+// factor 8 for the upwind axis velocity at Mach 10 -- so it is evaluated in
+// double like the temperature it depends on.)
 template <typename C, typename M>
 __device__ __forceinline__ void equilibrium(const Macro<M>& q, const Model<M>& mm,
                                             const Model<C>& mc, C (&feq)[NV])
 {
-    const EqCoef<C> c = eq_coef<C, M>(q, mm);
+    (void)mc;
+    const EqCoef<M> c = eq_coef<M, M>(q, mm);
 #pragma unroll
-    for (int i = 0; i < NV; i++) feq[i] = feq_vel<C>(i, c, mc);
+    for (int i = 0; i < NV; i++) feq[i] = static_cast<C>(feq_vel<M>(i, c, mm));
 }
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_INFLOW = 2, BC_REFLECT = 3 };
@@ -202,6 +207,23 @@ __device__ __forceinline__ C nnd_neg_c(C e1, C e2, C& mprev)
     const C d = fmac(C(-0.5), m - mprev, e1);
     mprev = m;
     return d;
+}
+
+// The comparison variant of Sec. 3 (the original Kataoka-Tsutahara scheme):
+// the second-order upwind difference, g_{I+1/2} = f_I + e_0 / 2 for v > 0 and
+// f_{I+1} - e_2 / 2 for v < 0, i.e. the NND forms with the limited slope
+// replaced by the upwind one:
+//   v > 0:  (3 f_I - 4 f_{I-1} + f_{I-2}) / 2 = e_0 + (e_0 - e_-1) / 2,
+//   v < 0:  (-3 f_I + 4 f_{I+1} - f_{I+2}) / 2 = e_1 - (e_2 - e_1) / 2.
+template <typename C>
+__device__ __forceinline__ C up2_pos(C em1, C e0)
+{
+    return fmac(C(0.5), e0 - em1, e0);
+}
+template <typename C>
+__device__ __forceinline__ C up2_neg(C e1, C e2)
+{
+    return fmac(C(-0.5), e2 - e1, e1);
 }
 
 // Laplacian of Eq. (lp) from one part per axis: along an axis the velocity

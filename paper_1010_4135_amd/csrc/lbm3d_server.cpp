@@ -30,6 +30,7 @@ struct Ticket {
     lbm3d_solver* h = nullptr;
     enum { QUEUED, ACTIVE, DONE } state = QUEUED;
     bool cancel = false;
+    bool waited = false;  // a thread waits on it (a second waiter gets E_STATE)
     int32_t status = LBM3D_OK;
     uint32_t health = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
@@ -54,7 +55,9 @@ struct lbm3d_server {
     bool membership_changed = true;
     std::thread worker;
     hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     lbm3d::BatchPlan plans[3];  // one per precision
+    lbm3d_server_counters stats{};  // guarded by mu
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void run();
@@ -90,6 +93,8 @@ void lbm3d_server::finish(Ticket* t, int32_t status)
 void lbm3d_server::run()
 {
     (void)hipSetDevice(device);
+    using lbm3d::BatchPlan;
+    auto secs = [](Clock::time_point a) { return std::chrono::duration<double>(Clock::now() - a).count(); };
     for (;;) {
         std::vector<Ticket*> admit;
         std::vector<Ticket*> cancelled;
@@ -125,6 +130,7 @@ void lbm3d_server::run()
             if (stop && admit.empty() && active.empty()) return;
         }
         // new solves: allocate and initialise outside the lock
+        const auto ta = Clock::now();
         for (Ticket* t : admit) {
             lbm3d_solver* h = nullptr;
             int32_t rc = lbm3d_create(&t->p, &h);
@@ -143,7 +149,9 @@ void lbm3d_server::run()
             t->state = Ticket::ACTIVE;
             active.push_back(t);
             membership_changed = true;
+            stats.admitted++;
         }
+        const double admit_s = admit.empty() ? 0.0 : secs(ta);
         // evict cancelled solves
         for (Ticket* t : cancelled) {
             {
@@ -159,38 +167,76 @@ void lbm3d_server::run()
             act = active;
             rebuild = membership_changed;
             membership_changed = false;
+            stats.admit_s += admit_s;
         }
         if (act.empty()) continue;
         // one tick: every precision group advances by the same number of
-        // steps, at most tick_steps and at most what its members still need
+        // steps, at most tick_steps and at most what its members still need.
+        // A plan rebuilt for a new membership runs its first tick with
+        // direct launches; a graph is captured only for a membership that
+        // has lasted a tick (its replays then pay for the capture).
         int32_t err = LBM3D_OK;
+        double plan_s = 0.0;
+        int rebuilds = 0;
+        std::vector<Ticket*> members_of[3];
+        (void)hipEventRecord(ev0, stream);
         for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++) {
             std::vector<lbm3d_solver*> members;
             int64_t k = tick_steps;
             for (Ticket* t : act)
                 if (t->h->mode == mode) {
                     members.push_back(t->h);
+                    members_of[mode].push_back(t);
                     k = std::min(k, t->left);
                 }
             if (members.empty() || k <= 0) continue;
-            if (rebuild || plans[mode].ntiles() == 0) err = plans[mode].build(members, stream);
-            if (err == LBM3D_OK) err = plans[mode].run(k, stream);
-            if (err == LBM3D_OK)
-                for (Ticket* t : act)
-                    if (t->h->mode == mode) t->left -= k;
-        }
-        if (err == LBM3D_OK && hipStreamSynchronize(stream) != hipSuccess) err = LBM3D_E_DEVICE;
-        // completions (and every active solve if the tick failed)
-        for (Ticket* t : act) {
-            if (err == LBM3D_OK && t->left > 0) continue;
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                active.erase(std::find(active.begin(), active.end(), t));
+            const bool fresh = rebuild || plans[mode].ntiles() == 0;
+            if (fresh) {
+                const auto tp = Clock::now();
+                err = plans[mode].build(members, stream);
+                plan_s += secs(tp);
+                rebuilds++;
             }
-            uint32_t hw = 0;
-            if (err == LBM3D_OK) (void)lbm3d_status(t->h, &hw, nullptr);
-            finish(t, err != LBM3D_OK ? err : ((hw & LBM3D_HEALTH_NONFINITE) ? LBM3D_E_NONFINITE : LBM3D_OK));
+            if (err == LBM3D_OK) err = plans[mode].run(k, stream, !fresh);
+            if (err == LBM3D_OK)
+                for (Ticket* t : members_of[mode]) t->left -= k;
         }
+        (void)hipEventRecord(ev1, stream);
+        if (err == LBM3D_OK && hipStreamSynchronize(stream) != hipSuccess) err = LBM3D_E_DEVICE;
+        float busy_ms = 0.0f;
+        if (err == LBM3D_OK) (void)hipEventElapsedTime(&busy_ms, ev0, ev1);
+        // health of every member after the tick (one gather per precision):
+        // a solve that has gone non-finite stops now instead of running out
+        // its steps
+        std::vector<uint32_t> hw_of[3];
+        for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++)
+            if (!members_of[mode].empty()) err = plans[mode].health(hw_of[mode], stream);
+        // completions (and every active solve if the tick failed)
+        const auto tf = Clock::now();
+        int ndone = 0, nevict = 0;
+        for (int mode = 0; mode < 3; mode++) {
+            for (size_t j = 0; j < members_of[mode].size(); j++) {
+                Ticket* t = members_of[mode][j];
+                const uint32_t hw = (err == LBM3D_OK && j < hw_of[mode].size()) ? hw_of[mode][j] : 0u;
+                const bool bad = (hw & LBM3D_HEALTH_NONFINITE) != 0;
+                if (err == LBM3D_OK && t->left > 0 && !bad) continue;
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    active.erase(std::find(active.begin(), active.end(), t));
+                }
+                if (bad && t->left > 0) nevict++;
+                ndone++;
+                finish(t, err != LBM3D_OK ? err : (bad ? LBM3D_E_NONFINITE : LBM3D_OK));
+            }
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        stats.ticks++;
+        stats.rebuilds += rebuilds;
+        stats.plan_s += plan_s;
+        stats.busy_s += busy_ms * 1e-3;
+        stats.completed += ndone;
+        stats.evicted += nevict;
+        if (ndone) stats.finish_s += secs(tf);
     }
 }
 
@@ -206,13 +252,18 @@ int32_t lbm3d_server_create(size_t hbm_budget_bytes, int32_t max_active, lbm3d_s
     s->max_active = max_active;
     s->t0 = Clock::now();
     if (hipGetDevice(&s->device) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess) {
+        if (s->ev0) (void)hipEventDestroy(s->ev0);
+        if (s->stream) (void)hipStreamDestroy(s->stream);
         delete s;
         return LBM3D_E_DEVICE;
     }
     try {
         s->worker = std::thread([s] { s->run(); });
     } catch (...) {
+        (void)hipEventDestroy(s->ev0);
+        (void)hipEventDestroy(s->ev1);
         (void)hipStreamDestroy(s->stream);
         delete s;
         return LBM3D_E_NOMEM;
@@ -238,7 +289,8 @@ int32_t lbm3d_server_submit(lbm3d_server_t s, const lbm3d_params* p, const doubl
     int32_t rc = lbm3d_footprint(p, &fp);
     if (rc) return rc;
     if (fp > s->budget) return LBM3D_E_NOMEM;
-    if (!lbm3d::tiled_fits(p->precision, lbm3d::make_grid(p))) return LBM3D_E_INVAL;  // batched kernel's limit
+    // the batched kernel's limits: 32-bit plane offsets, NND only
+    if (!lbm3d::tiled_fits(p->precision, lbm3d::make_grid(p)) || (p->flags & LBM3D_UPWIND2)) return LBM3D_E_INVAL;
     const size_t n = (size_t)p->nx * p->ny * p->nz;
     for (size_t k = 0; k < n; k++)
         if (!(rho[k] > 0.0) || !(pr[k] > 0.0)) return LBM3D_E_INVAL;
@@ -284,7 +336,12 @@ int32_t lbm3d_server_wait(lbm3d_server_t s, uint64_t ticket, double* rho, double
         auto it = s->tickets.find(ticket);
         if (it == s->tickets.end()) return LBM3D_E_NOTFOUND;
         Ticket* tp = it->second.get();
+        // one waiter per ticket: the ticket (and its map entry) is released
+        // by the waiter that claimed it
+        if (tp->waited) return LBM3D_E_STATE;
+        tp->waited = true;
         s->cv_done.wait(lk, [tp] { return tp->state == Ticket::DONE; });
+        it = s->tickets.find(ticket);  // (the map may have rehashed meanwhile)
         t = std::move(it->second);
         s->tickets.erase(it);
     }
@@ -299,6 +356,15 @@ int32_t lbm3d_server_wait(lbm3d_server_t s, uint64_t ticket, double* rho, double
         tm->health = t->health;
     }
     return t->status;
+}
+
+int32_t lbm3d_server_stats(lbm3d_server_t s, lbm3d_server_counters* out)
+{
+    if (!s || !out) return LBM3D_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    out->wall_s = s->now();
+    return LBM3D_OK;
 }
 
 int32_t lbm3d_server_cancel(lbm3d_server_t s, uint64_t ticket)
@@ -323,6 +389,9 @@ int32_t lbm3d_server_destroy(lbm3d_server_t s)
     }
     if (s->worker.joinable()) s->worker.join();
     (void)hipStreamSynchronize(s->stream);
+    for (auto& pl : s->plans) pl.build({}, s->stream);  // drop the plans' graphs and tables first
+    (void)hipEventDestroy(s->ev0);
+    (void)hipEventDestroy(s->ev1);
     (void)hipStreamDestroy(s->stream);
     delete s;
     return LBM3D_OK;

@@ -10,8 +10,10 @@
 // over the eigenvalues omega of G.  Host code only: no device call.
 #include "lbm3d_api_impl.h"
 
+#include <array>
 #include <cmath>
 #include <complex>
+#include <vector>
 
 namespace lbm3d {
 namespace {
@@ -110,9 +112,61 @@ double spectral_radius(cd (&G)[NV][NV])
 }
 
 }  // namespace
+
+// max |omega| over k dx in [0, pi] (nk points) along `axis` for state q.
+static double scan(const lbm3d_params* p, const double q[5], int axis, int nk, double* kdx_at)
+{
+    double om = 0.0, k = 0.0;
+    if (lbm3d_stability(p, q, axis, 0.0, 3.14159265358979323846, nk, 0.0, &om, &k) != LBM3D_OK) return INFINITY;
+    if (kdx_at) *kdx_at = k;
+    return om;
+}
+
+int32_t admission(const lbm3d_params* p, const double* rho, const double* ux, const double* uy, const double* uz,
+                  const double* pr, double* worst)
+{
+    const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    if (n < 1) return LBM3D_E_INVAL;
+    // the states at which the linearised scheme is least stable lie at the
+    // extremes of the initial fields: the fastest node, the coldest and the
+    // hottest; fixed inflow states are added
+    int64_t kmax_u = 0, kmin_t = 0, kmax_t = 0;
+    double best_u = -1.0, best_lo = INFINITY, best_hi = -INFINITY;
+    for (int64_t k = 0; k < n; k++) {
+        if (!(rho[k] > 0.0) || !(pr[k] > 0.0)) return LBM3D_E_INVAL;
+        const double u2 = ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k];
+        const double T = pr[k] / rho[k];
+        if (u2 > best_u) { best_u = u2; kmax_u = k; }
+        if (T < best_lo) { best_lo = T; kmin_t = k; }
+        if (T > best_hi) { best_hi = T; kmax_t = k; }
+    }
+    std::vector<std::array<double, 5>> states;
+    for (int64_t k : {kmax_u, kmin_t, kmax_t})
+        states.push_back({rho[k], ux[k], uy[k], uz[k], pr[k] / rho[k]});
+    for (int face = 0; face < 6; face++)
+        if (p->bc[face] == LBM3D_INFLOW) {
+            const double* st = p->inflow[face];
+            states.push_back({st[0], st[1], st[2], st[3], st[4] / st[0]});
+        }
+    double w = 0.0;
+    for (const auto& q : states)
+        for (int axis = 0; axis < 4; axis++) w = std::fmax(w, scan(p, q.data(), axis, 33, nullptr));
+    if (worst) *worst = w;
+    return w > 1.0 + STABILITY_TOL ? LBM3D_E_UNSTABLE : LBM3D_OK;
+}
+
 }  // namespace lbm3d
 
 using namespace lbm3d;
+
+extern "C" int32_t lbm3d_admit(const lbm3d_params* p, const double* rho, const double* ux, const double* uy,
+                               const double* uz, const double* pr, double* max_omega)
+{
+    if (!p || !rho || !ux || !uy || !uz || !pr) return LBM3D_E_INVAL;
+    const int32_t v = validate(p);
+    if (v != LBM3D_OK) return v;
+    return admission(p, rho, ux, uy, uz, pr, max_omega);
+}
 
 extern "C" int32_t lbm3d_stability(const lbm3d_params* p, const double* q, int32_t axis, double kdx_lo,
                                    double kdx_hi, int32_t nk, double alpha_t, double* max_omega,
@@ -146,7 +200,14 @@ extern "C" int32_t lbm3d_stability(const lbm3d_params* p, const double* q, int32
                 const cd e = std::polar(1.0, thv[a]);
                 const double va = s.v[i][a];
                 if (va != 0.0) {
-                    const cd phi = va > 0.0 ? (1.0 - alpha_t) * (1.0 - std::conj(e)) : (1.0 - alpha_t) * (e - 1.0);
+                    // NND, linearised; or the second-order upwind difference
+                    // (3 - 4 e^{-ik} + e^{-2ik}) / 2, mirrored for v < 0
+                    cd phi;
+                    if (p->flags & LBM3D_UPWIND2)
+                        phi = va > 0.0 ? 0.5 * (3.0 - 4.0 * std::conj(e) + std::conj(e * e))
+                                       : 0.5 * (-3.0 + 4.0 * e - e * e);
+                    else
+                        phi = va > 0.0 ? (1.0 - alpha_t) * (1.0 - std::conj(e)) : (1.0 - alpha_t) * (e - 1.0);
                     diag -= m.k_adv * va * phi;
                 }
                 diag += lam[grp] * (2.0 * std::cos(thv[a]) - 2.0);

@@ -33,23 +33,6 @@
 
 namespace lbm3d {
 
-// Build-time tuning knob: tiles are numbered with x fastest (1) or y
-// fastest (0) before the XCD grouping.
-#ifndef LBM3D_TILE_ORDER_X
-#define LBM3D_TILE_ORDER_X 1
-#endif
-// LBM3D_LOAD_INTERLEAVE: the loads of the planes ahead are issued one per
-// velocity between the updates (1) or together before the barrier (0).
-#ifndef LBM3D_LOAD_INTERLEAVE
-#define LBM3D_LOAD_INTERLEAVE 1
-#endif
-// LBM3D_VCONST: FP64 model constants of the moments and the equilibrium
-// kept in vector registers by the 8-row tiles of the FP32_T64 mode (1: the
-// equilibrium coefficients, 2: those and the moment constants, 0: none,
-// left to the scalar registers).
-#ifndef LBM3D_VCONST
-#define LBM3D_VCONST 2
-#endif
 
 // Workgroup barrier that orders LDS accesses only: global loads in flight
 // (the prefetch of the planes ahead) and global stores are not drained.
@@ -275,20 +258,13 @@ __device__ __forceinline__ S ld_at(const S* base, uint32_t off)
 // Stores of the new level are streaming (non-temporal): they are not read
 // again in this step, and keeping them out of the L2 leaves it to the
 // planes that neighbouring tiles read as their halos.
-#ifndef LBM3D_NT_STORE
-#define LBM3D_NT_STORE 1
-#endif
 template <typename S>
 __device__ __forceinline__ void st_at(S* base, uint32_t off, S v)
 {
     using GP = __attribute__((address_space(1))) S*;
     asm("" : "+v"(off));
     GP p = reinterpret_cast<GP>(reinterpret_cast<uint64_t>(base) + (uint64_t)off);
-#if LBM3D_NT_STORE
     __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
 }
 
 // Index v in [-2, n + 9] wrapped into [0, n) (periodic faces).
@@ -336,7 +312,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     constexpr uint32_t ES = sizeof(S);
     const Model<C>& mc = pick<C>(md, mf);
     Model<M> mm = pick<M>(md, mf);
-    if constexpr (VK && MODE == MODE_FP32_T64 && BY >= 8 && LBM3D_VCONST > 0) {
+    if constexpr (VK && MODE == MODE_FP32_T64 && BY >= 8) {
         // Uniform FP64 constants held in vector registers.  The scalar
         // file cannot hold them beside the pointers and loop state, and the
         // compiler would spill them into vector lanes and read them back
@@ -348,9 +324,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
         vk(mm.r_aT);
         vk(mm.x_a0); vk(mm.x_aT); vk(mm.x_au); vk(mm.x_b0); vk(mm.x_bT); vk(mm.x_bu);
         vk(mm.d_a0); vk(mm.d_aT); vk(mm.d_au); vk(mm.d_b0); vk(mm.d_bT); vk(mm.d_bu);
-        if constexpr (LBM3D_VCONST > 1) {
-            vk(mm.c1); vk(mm.k); vk(mm.e0sq); vk(mm.c1sq); vk(mm.c2sq); vk(mm.inv_b);
-        }
+        vk(mm.c1); vk(mm.k); vk(mm.e0sq); vk(mm.c1sq); vk(mm.c2sq); vk(mm.inv_b); vk(mm.x_d); vk(mm.d_d);
     }
     const Grid& g = A.g;
     const S* __restrict__ f = A.f;
@@ -373,12 +347,12 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     // Other layers are read from memory.  Every load is clamped into the
     // padded array: nodes beyond the last layer are never read by an
     // active node's stencil.
-    const bool xin_tile = LBM3D_X_IN_TILE && (g.nx % TILE_X) == 0;
+    const bool xin_tile = (g.nx % TILE_X) == 0;
     const bool lf = xin_tile && x0 == 0, rf = xin_tile && x0 + TILE_X == g.nx;
     const int kL = A.bc.kind[0], kR = A.bc.kind[1];
-    const bool xwrap = LBM3D_WRAP && kL == BC_PERIODIC;
-    const bool ywrap = LBM3D_WRAP && A.bc.kind[2] == BC_PERIODIC;
-    const bool zwrap = LBM3D_WRAP && A.bc.kind[4] == BC_PERIODIC;
+    const bool xwrap = kL == BC_PERIODIC;
+    const bool ywrap = A.bc.kind[2] == BC_PERIODIC;
+    const bool zwrap = A.bc.kind[4] == BC_PERIODIC;
     // x wrapped into [0, nx) for the columns a stencil can read (-2 .. nx+1);
     // columns further right only feed lanes outside the grid
     auto xw = [&](int v) {
@@ -521,7 +495,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
         M c, m;
         layer_coefs(kind, j + 1, c, m);
         const Macro<M> qs = layer_state(q0, q1, c, m, 0);
-        const C val = feq_vel<C>(iv, eq_coef<C, M>(qs, mm), mc);
+        const C val = static_cast<C>(feq_vel<M>(iv, eq_coef<M, M>(qs, mm), mm));
         if (on) T.v[iv][ty + 2][side ? TILE_X + 2 + j : 1 - j] = static_cast<S>(val);
     };
 
@@ -553,7 +527,6 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
             q[I][(K + 3) & 3] = static_cast<C>(ld_at(p, colb));
             pa += sv;
         };
-        if constexpr (!LBM3D_LOAD_INTERLEAVE) static_for<NV>(ring_load);
         load_halo(K & 1, za);
         za = znext(za);
         zb = znext(zb);
@@ -626,7 +599,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
             po = sreg(po);
             st_at(po, outb, static_cast<S>(out));
             po += sv;
-            if constexpr (LBM3D_LOAD_INTERLEAVE) ring_load(ic);
+            ring_load(ic);
         });
 
         // stage plane z+1: own values and its halo
@@ -654,7 +627,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
 template <int MODE>
 __device__ __forceinline__ bool x_forms(const StepArgs<MODE>& A, int x0)
 {
-    if (!LBM3D_X_IN_TILE || (A.g.nx % TILE_X) != 0) return false;
+    if ((A.g.nx % TILE_X) != 0) return false;
     auto formed = [](int k) { return k == BC_OUTFLOW || k == BC_REFLECT; };
     return (x0 == 0 && formed(A.bc.kind[0])) || (x0 + TILE_X == A.g.nx && formed(A.bc.kind[1]));
 }

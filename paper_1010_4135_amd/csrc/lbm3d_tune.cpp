@@ -92,8 +92,9 @@ extern "C" int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t*
     TileCfg best = h->tile;
     float best_ms = -1.0f;
     for (const TileCfg& t : tile_candidates(h->mode, h->g)) {
+        if (h->upwind2 && t.by != 0) continue;  // the variant runs untiled only
         auto launch = [&]() {
-            return launch_step(h->mode, h->g, h->bc, t, h->md, h->mf, h->p.inflow, f, fn, h->health, s);
+            return launch_step(h->mode, h->g, h->bc, t, h->md, h->mf, h->p.inflow, f, fn, h->health, s, h->upwind2);
         };
         for (int w = 0; w < 2 && e == hipSuccess; w++) e = launch();
         if (e == hipSuccess) e = hipEventRecord(h->ev0, s);
@@ -119,16 +120,18 @@ extern "C" int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t*
     return LBM3D_OK;
 }
 
+extern "C" int32_t lbm3d_batch_set_depth(int32_t precision, int32_t tz)
+{
+    if (precision < LBM3D_FP64 || precision > LBM3D_FP32_T64 || tz < 0 || tz > 65535) return LBM3D_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_batch_tz[precision] = tz;
+    return LBM3D_OK;
+}
+
 extern "C" int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches, int32_t* tz)
 {
-    if (!hs || count < 1) return LBM3D_E_INVAL;
-    std::set<lbm3d_t> seen;
-    for (int32_t k = 0; k < count; k++) {
-        if (!hs[k] || !seen.insert(hs[k]).second) return LBM3D_E_INVAL;
-        if (!hs[k]->initialised) return LBM3D_E_STATE;
-        if (hs[k]->mode != hs[0]->mode) return LBM3D_E_INVAL;
-        if (!tiled_fits(hs[k]->mode, hs[k]->g)) return LBM3D_E_INVAL;
-    }
+    int32_t rc = check_batch(hs, count);
+    if (rc) return rc;
     if (launches <= 0) launches = 5;
     hipStream_t s = hs[0]->stream;
     for (int32_t k = 0; k < count; k++)
@@ -139,11 +142,12 @@ extern "C" int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches
     if (e == hipSuccess) e = hipEventCreate(&e1);
     int best_tz = 0;
     float best_ms = -1.0f;
-    const int tzs[3] = {8, 16, 32};
+    // chunk depths; a depth at or beyond a member's nz gives whole columns
+    const int tzs[4] = {16, 32, 64, 128};
     for (int t : tzs) {
         if (e != hipSuccess) break;
         BatchPlan plan;
-        int32_t rc = plan.build(members, s, t);
+        rc = plan.build(members, s, t);
         if (rc) {
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);

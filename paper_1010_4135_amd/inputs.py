@@ -181,6 +181,56 @@ def shock_bubble(seed: int, grid=(256, 128, 128), steps: int = 2000, precision=F
                      radius=r))
 
 
+# The paper's own shock-bubble and shock-droplet runs (Sec. 4 (2), Eqs.
+# (light) and (heavy)).
+PAPER_BUBBLE_MODEL = dict(c1=2.0, c2=6.0, eta0=4.0, gamma=1.4, tau=1e-5, dt=1e-5, dx=0.001)
+PAPER_POST_SHOCK = (2.66667, -1.47902, 0.0, 0.0, 4.5)  # p = 4.5 (the printed 3.94406 is rho |u|)
+PAPER_SPHERE_DENSITY = {"bubble": 0.1358, "droplet": 4.1538}
+
+
+def paper_shock_bubble(kind: str = "bubble", precision=FP64, radius: float = 20.0, shock_x: float = 230.0,
+                       smooth: float = 1.0, steps: int = 10000) -> Case:
+    """The paper's planar Mach-2 shock running right to left into a light
+    bubble (rho = 0.1358) or a heavy droplet (rho = 4.1538) at rest with
+    p = 1, in quiescent gas (1, 0, 0, 0, 1).  The paper's node indices run
+    over (0:301, 0:81, 0:81) and include the two boundary-node layers of
+    every face, so the interior is 298 x 78 x 78 and the sphere's centre,
+    node (200, 40, 40), is interior node (198, 38, 38).  Faces: the post-shock
+    state fixed at +x, extrapolation at -x, reflecting walls in y and z.
+    (c1, c2, eta0) = (2, 6, 4), gamma = 1.4, dx = 0.001, dt = tau = 1e-5;
+    t = 0.1 is 10000 steps.  Not stated by the paper and chosen here: the
+    sphere's radius (20 nodes, half the tube's width across), the shock's
+    start (paper node x = 230, 10 nodes to the right of the sphere) and a
+    density jump blended over `smooth` cells (0: a sharp, stair-stepped
+    surface)."""
+    if kind not in PAPER_SPHERE_DENSITY:
+        raise ValueError(f"kind must be one of {sorted(PAPER_SPHERE_DENSITY)}")
+    grid = (298, 78, 78)
+    nx, ny, nz = grid
+    prm = make_params(grid, (OUTFLOW, INFLOW, REFLECT, REFLECT, REFLECT, REFLECT),
+                      inflow={1: PAPER_POST_SHOCK}, precision=precision, **PAPER_BUBBLE_MODEL)
+    # interior node i is the paper's node i + 2
+    cx, cy, cz = 200.0 - 2, 40.0 - 2, 40.0 - 2
+    xs = shock_x - 2
+    zz, yy, xx = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                             np.arange(nx, dtype=np.float64), indexing="ij")
+    dist = np.sqrt((xx - cx) ** 2 + (yy - cy) ** 2 + (zz - cz) ** 2)
+    inside = PAPER_SPHERE_DENSITY[kind]
+    if smooth > 0:
+        rho = 1.0 + (inside - 1.0) * 0.5 * (1.0 - np.tanh((dist - radius) / smooth))
+    else:
+        rho = np.where(dist <= radius, inside, 1.0)
+    ux = np.zeros_like(rho)
+    p = np.ones_like(rho)
+    post = xx > xs
+    rho[post] = PAPER_POST_SHOCK[0]
+    ux[post] = PAPER_POST_SHOCK[1]
+    p[post] = PAPER_POST_SHOCK[4]
+    z = np.zeros_like(rho)
+    return Case(f"paper_shock_{kind}", 0, prm, (rho, ux, z, z.copy(), p), steps,
+                dict(kind=kind, radius=radius, shock_x=shock_x, centre=(cx, cy, cz), smooth=smooth))
+
+
 def batch_cases(seed: int, count: int = 64, steps: int = 500, precision=FP32_T64,
                 grids=BATCH_GRIDS) -> list:
     """Independent solves of uneven size: grid drawn from `grids`, a 3D

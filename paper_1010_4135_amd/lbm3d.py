@@ -20,7 +20,7 @@ OK, E_INVAL, E_UNSTABLE, E_NOMEM, E_DEVICE, E_STATE, E_NONFINITE, E_NOTFOUND, E_
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, FP32, FP32_T64 = 0, 1, 2
 PERIODIC, OUTFLOW, INFLOW, REFLECT = 0, 1, 2, 3
-NO_DISSIPATION = 1
+NO_DISSIPATION, UPWIND2, CHECK_STABILITY = 1, 2, 4
 HEALTH_NONFINITE, HEALTH_RHO_NONPOS, HEALTH_T_NONPOS = 1, 2, 4
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_t64": FP32_T64}
 NV = 15
@@ -51,6 +51,13 @@ class lbm3d_timing(ctypes.Structure):
                 ("health", ctypes.c_uint32)]
 
 
+class lbm3d_server_counters(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_int64), ("rebuilds", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("evicted", ctypes.c_int64), ("wall_s", ctypes.c_double),
+                ("busy_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("plan_s", ctypes.c_double),
+                ("finish_s", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"lbm3d HIP library not built: {LIB_PATH} is missing "
@@ -74,22 +81,28 @@ def _load():
         "lbm3d_set_tile": (I32, [P, I32, I32]),
         "lbm3d_tune": (I32, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "lbm3d_batch_tune": (I32, [ctypes.POINTER(P), I32, I32, ctypes.POINTER(I32)]),
+        "lbm3d_batch_set_depth": (I32, [I32, I32]),
         "lbm3d_get_tile": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "lbm3d_sync": (I32, [P]),
         "lbm3d_stream_copy_rate": (I32, [I64, I32, D]),
+        "lbm3d_admit": (I32, [PP, D, D, D, D, D, D]),
         "lbm3d_stability": (I32, [PP, D, I32, ctypes.c_double, ctypes.c_double, I32, ctypes.c_double, D, D]),
         "lbm3d_moments": (I32, [P, D, D, D, D, D]),
         "lbm3d_conserved": (I32, [P, D]),
         "lbm3d_status": (I32, [P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(I64)]),
         "lbm3d_get_f": (I32, [P, P, SZ]),
+        "lbm3d_poison_next": (I32, [P]),
         "lbm3d_set_f": (I32, [P, P, SZ]),
         "lbm3d_batch_step": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(I64)]),
+        "lbm3d_batch_plan": (I32, [PP, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                   ctypes.POINTER(I32), I64, ctypes.POINTER(I32)]),
         "lbm3d_server_create": (I32, [SZ, I32, ctypes.POINTER(P)]),
         "lbm3d_server_set_tick": (I32, [P, I64]),
         "lbm3d_server_submit": (I32, [P, PP, D, D, D, D, D, I64, ctypes.POINTER(U64)]),
         "lbm3d_server_poll": (I32, [P, U64, ctypes.POINTER(I32)]),
         "lbm3d_server_wait": (I32, [P, U64, D, D, D, D, D, ctypes.POINTER(lbm3d_timing)]),
         "lbm3d_server_cancel": (I32, [P, U64]),
+        "lbm3d_server_stats": (I32, [P, ctypes.POINTER(lbm3d_server_counters)]),
         "lbm3d_server_destroy": (I32, [P]),
     }
     for name, (res, args) in sig.items():
@@ -242,6 +255,19 @@ def lbm3d_stability(params: dict, q, axis: int = 0, kdx=(0.0, np.pi), nk: int = 
     return om.value, kk.value
 
 
+def lbm3d_admit(params, fields):
+    """Stability admission of an initial state: (status, max |omega|) with
+    status OK or E_UNSTABLE (other errors raise)."""
+    p = _params(params)
+    n = p.nx * p.ny * p.nz
+    arrs = _fields5(fields, n)
+    om = ctypes.c_double(0.0)
+    rc = _lib.lbm3d_admit(ctypes.byref(p), *[_dp(a) for a in arrs], ctypes.byref(om))
+    if rc not in (OK, E_UNSTABLE):
+        _check(rc, "lbm3d_admit")
+    return rc, om.value
+
+
 def lbm3d_stream_copy_rate(nbytes: int, launches: int = 10) -> float:
     """GB/s (read + written) of a plain copy alternating between two device
     buffers of nbytes each: the practical ceiling of an HBM-bound kernel."""
@@ -278,6 +304,10 @@ def lbm3d_get_f(h, shape, precision: int) -> np.ndarray:
     return out
 
 
+def lbm3d_poison_next(h):
+    _check(_lib.lbm3d_poison_next(h), "lbm3d_poison_next")
+
+
 def lbm3d_set_f(h, f: np.ndarray):
     f = np.ascontiguousarray(f)
     _check(_lib.lbm3d_set_f(h, f.ctypes.data_as(ctypes.c_void_p), f.nbytes), "lbm3d_set_f")
@@ -287,6 +317,27 @@ def lbm3d_batch_step(handles, nsteps):
     arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
     ns = (ctypes.c_int64 * len(handles))(*[int(n) for n in nsteps])
     _check(_lib.lbm3d_batch_step(arr, len(handles), ns), "lbm3d_batch_step")
+
+
+def lbm3d_batch_set_depth(precision, tz: int):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(_lib.lbm3d_batch_set_depth(prec, int(tz)), "lbm3d_batch_set_depth")
+
+
+def lbm3d_batch_plan(params_list, tz: int = 0, cus: int = 256):
+    """Host-side work plan of the batched step: (tiles, list_first, nblocks)
+    with tiles an (n, 7) int32 array of (solve, x0, x1, y0, y1, z0, z1)."""
+    arr = (lbm3d_params * len(params_list))(*[_params(p) for p in params_list])
+    nt, nl, nb = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(_lib.lbm3d_batch_plan(arr, len(params_list), int(tz), int(cus), ctypes.byref(nt), ctypes.byref(nl),
+                                 ctypes.byref(nb), None, 0, None), "lbm3d_batch_plan")
+    tiles = np.zeros((max(nt.value, 1), 7), dtype=np.int32)
+    first = np.zeros(9, dtype=np.int32)
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    _check(_lib.lbm3d_batch_plan(arr, len(params_list), int(tz), int(cus), None, None, None,
+                                 tiles.ctypes.data_as(I32P), tiles.shape[0], first.ctypes.data_as(I32P)),
+           "lbm3d_batch_plan")
+    return tiles[:nt.value], first[:nl.value + 1], nb.value
 
 
 def lbm3d_batch_tune(handles, launches: int = 5) -> int:
@@ -328,10 +379,16 @@ def lbm3d_server_wait(s, ticket: int, shape):
     out = [np.empty(shape, dtype=np.float64) for _ in range(5)]
     t = lbm3d_timing()
     rc = _lib.lbm3d_server_wait(s, ctypes.c_uint64(ticket), *[_dp(a) for a in out], ctypes.byref(t))
-    if rc not in (OK, E_NONFINITE, E_CANCELLED):
+    if rc not in (OK, E_NONFINITE, E_CANCELLED, E_UNSTABLE):
         raise LbmError(rc, "lbm3d_server_wait")
     timing = dict(t_submit=t.t_submit, t_admit=t.t_admit, t_done=t.t_done, steps=t.steps, health=t.health)
     return rc, tuple(out), timing
+
+
+def lbm3d_server_stats(s) -> dict:
+    st = lbm3d_server_counters()
+    _check(_lib.lbm3d_server_stats(s, ctypes.byref(st)), "lbm3d_server_stats")
+    return {name: getattr(st, name) for name, _ in lbm3d_server_counters._fields_}
 
 
 def lbm3d_server_cancel(s, ticket: int):
@@ -408,6 +465,9 @@ class Solver:
     def set_f(self, f):
         lbm3d_set_f(self.h, f)
 
+    def poison_next(self):
+        lbm3d_poison_next(self.h)
+
 
 class Server:
     """Continuous-batching server: ``Server(budget_bytes, max_active)``;
@@ -429,6 +489,9 @@ class Server:
 
     def cancel(self, ticket: int):
         lbm3d_server_cancel(self.s, ticket)
+
+    def stats(self) -> dict:
+        return lbm3d_server_stats(self.s)
 
     def close(self):
         if self.s is not None and self.s.value:

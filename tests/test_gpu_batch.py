@@ -1,12 +1,28 @@
 """Batched stepping on the GPU: many solves of uneven size advanced by one
-persistent launch per step must give each solve bitwise the result it gets
-alone, for any mix of sizes, boundary kinds and step counts."""
+persistent launch per step.
+
+- Every member matches the FP64 oracle run alone on the same input: in FP64
+  to the FP64 bar (relative L1 <= 1e-12 per field, f elementwise within
+  1e-11 of max|f|), in the FP32 modes within FP32_SHORT_TOL.
+- Every member's distributions are bitwise those it gets stepped alone
+  through the library, for any mix of sizes, boundary kinds, step counts and
+  tile depths (whole columns included), and for members whose row or plane
+  indices exceed 16 bits.
+"""
 import numpy as np
 import pytest
 
-from paper_1010_4135_amd import inputs
+import oracle
+from paper_1010_4135_amd import inputs, metrics
 
 pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+# FP32 modes against the FP64 oracle after at most 40 steps: 15-term sums in
+# float carry ~1e-6 relative rounding per step, not amplified by the
+# dissipative scheme; at the shocks of these short runs a rounding-sized
+# shift moves single nodes.  Measured values are printed (1e-7 to 3e-6).
+FP32_SHORT_TOL = 2e-5
 
 
 def _lib():
@@ -26,6 +42,9 @@ def _mix(precision):
     ]
 
 
+STEPS = [40, 23, 40, 1, 17, 30, 12]
+
+
 def _alone(case, steps):
     s = _lib().Solver(dict(case.params))
     s.init(*case.fields)
@@ -35,23 +54,92 @@ def _alone(case, steps):
     return f
 
 
-@pytest.mark.parametrize("precision", ["fp32_t64", "fp64", "fp32"])
-def test_batch_equals_alone_bitwise(precision):
+def _oracle(case, steps):
+    o = oracle.Oracle(dict(case.params))
+    o.init(*case.fields)
+    o.step(steps)
+    return o
+
+
+def _batched(cases, steps, split=True):
     lbm3d = _lib()
-    cases = _mix(precision)
-    steps = [40, 23, 40, 1, 17, 30, 12]
     solvers = []
     for c in cases:
         s = lbm3d.Solver(dict(c.params))
         s.init(*c.fields)
         solvers.append(s)
-    # a first batched run, then a second one with a different membership
-    lbm3d.lbm3d_batch_step([s.h for s in solvers], [k // 2 for k in steps])
-    lbm3d.lbm3d_batch_step([s.h for s in solvers], [k - k // 2 for k in steps])
-    for c, s, k in zip(cases, solvers, steps):
+    if split:
+        # a first batched run, then a second one with a different membership
+        lbm3d.lbm3d_batch_step([s.h for s in solvers], [k // 2 for k in steps])
+        lbm3d.lbm3d_batch_step([s.h for s in solvers], [k - k // 2 for k in steps])
+    else:
+        lbm3d.lbm3d_batch_step([s.h for s in solvers], list(steps))
+    return solvers
+
+
+@pytest.mark.parametrize("precision", ["fp32_t64", "fp64", "fp32"])
+def test_batch_members_match_oracle_and_solo_runs(precision):
+    cases = _mix(precision)
+    solvers = _batched(cases, STEPS)
+    for c, s, k in zip(cases, solvers, STEPS):
         _, done = s.status()
         assert done == k
-        assert np.array_equal(s.get_f(), _alone(c, k)), c.name
+        fb = s.get_f()
+        assert np.array_equal(fb, _alone(c, k)), c.name
+        o = _oracle(c, k)
+        err = metrics.rel_l1(s.moments(), o.moments())
+        print(f"[batch {precision} {c.name} {c.grid} {k} steps] " +
+              " ".join(f"{a}={v:.2e}" for a, v in err.items()), flush=True)
+        if precision == "fp64":
+            assert max(err.values()) <= FP64_TOL, (c.name, err)
+            fo = o.get_f()
+            assert np.abs(fb - fo).max() <= 1e-11 * np.abs(fo).max(), c.name
+        else:
+            assert max(err.values()) <= FP32_SHORT_TOL, (c.name, err)
+        s.close()
+
+
+@pytest.mark.parametrize("tz", [16, 64, 128])
+def test_batch_tile_depths_are_bitwise_equal(tz):
+    """The tile depth (whole columns at 128 here) changes only the work
+    split, never a result."""
+    lbm3d = _lib()
+    cases = _mix("fp32_t64")
+    solvers = []
+    for c in cases:
+        s = lbm3d.Solver(dict(c.params))
+        s.init(*c.fields)
+        solvers.append(s)
+    lbm3d.lbm3d_batch_set_depth("fp32_t64", tz)
+    try:
+        lbm3d.lbm3d_batch_step([s.h for s in solvers], STEPS)
+    finally:
+        lbm3d.lbm3d_batch_set_depth("fp32_t64", 0)
+    for c, s, k in zip(cases, solvers, STEPS):
+        assert np.array_equal(s.get_f(), _alone(c, k)), (tz, c.name)
+        s.close()
+
+
+@pytest.mark.parametrize("grid", [(64, 1, 40000), (8, 262200, 1)], ids=["planes40000", "rows262200"])
+def test_batch_member_with_indices_beyond_16_bits(grid):
+    """A member with 40000 planes (z index beyond 32767), or 262200 rows
+    (32775 row tiles of 8), batched with a small one, is bitwise equal to
+    its solo run."""
+    lbm3d = _lib()
+    big = inputs.smooth_periodic(31, grid=grid, amp=0.2, precision="fp32")
+    small = inputs.smooth_periodic(32, grid=(32, 16, 8), amp=0.2, precision="fp32")
+    print(f"[batch beyond 16 bits] grid {grid}", flush=True)
+    solvers = []
+    for c in (big, small):
+        s = lbm3d.Solver(dict(c.params))
+        s.init(*c.fields)
+        solvers.append(s)
+    lbm3d.lbm3d_batch_step([s.h for s in solvers], [5, 3])
+    assert np.array_equal(solvers[0].get_f(), _alone(big, 5))
+    assert np.array_equal(solvers[1].get_f(), _alone(small, 3))
+    h, done = solvers[0].status()
+    assert done == 5 and not (h & 1)
+    for s in solvers:
         s.close()
 
 
@@ -67,6 +155,9 @@ def test_batch_rejects_bad_arguments():
     assert ei.value.code == lbm3d.E_INVAL
     with pytest.raises(lbm3d.LbmError) as ei:
         lbm3d.lbm3d_batch_step([a.h, a.h], [1, 1])
+    assert ei.value.code == lbm3d.E_INVAL
+    with pytest.raises(lbm3d.LbmError) as ei:
+        lbm3d.lbm3d_batch_step([a.h], [-1])
     assert ei.value.code == lbm3d.E_INVAL
     d = lbm3d.Solver(c.params)
     with pytest.raises(lbm3d.LbmError) as ei:
@@ -87,7 +178,7 @@ def test_batch_autotuner_keeps_states():
         solvers.append(s)
     before = [s.get_f() for s in solvers]
     tz = lbm3d.lbm3d_batch_tune([s.h for s in solvers], 3)
-    assert tz in (8, 16, 32)
+    assert tz in (16, 32, 64, 128)
     for s, f in zip(solvers, before):
         assert np.array_equal(s.get_f(), f) and s.status()[1] == 3
     lbm3d.lbm3d_batch_step([s.h for s in solvers], [9] * len(solvers))

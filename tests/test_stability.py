@@ -74,3 +74,80 @@ def test_bad_arguments_are_rejected(kw):
     with pytest.raises(lbm3d.LbmError) as ei:
         lbm3d.lbm3d_stability(_params(8.0, 24.0, 8.0, 1.0 / 256), **args)
     assert ei.value.code == -1
+
+
+def _uniform_fields(grid, state):
+    nx, ny, nz = grid
+    return tuple(np.full((nz, ny, nx), v) for v in state)
+
+
+def test_admission_refuses_an_unstable_initial_state():
+    """(c1, c2, eta0) = (2, 6, 2), the paper's Lax-tube model, at the
+    post-shock state of a Mach-8 shock (u = 7.77, T = 13.4): the analysis
+    grows by several percent per step, so the state is refused; with the
+    paper's high-Mach model (8, 24, 8) the same state is admitted."""
+    rho2, u2, p2, _ = inputs.rankine_hugoniot(8.0)
+    fields = _uniform_fields((8, 8, 8), (rho2, u2, 0.0, 0.0, p2))
+    p = _params(2.0, 6.0, 2.0, 1.0 / 256)
+    rc, om = lbm3d.lbm3d_admit(p, fields)
+    assert rc == lbm3d.E_UNSTABLE and om > 1.01
+    rc, om = lbm3d.lbm3d_admit(_params(8.0, 24.0, 8.0, 1.0 / 256), fields)
+    assert rc == lbm3d.OK and om <= 1.001
+
+
+def test_admission_takes_the_extremes_of_the_fields():
+    """A stable background with one fast node: the fast node decides."""
+    rho2, u2, p2, _ = inputs.rankine_hugoniot(8.0)
+    rho, ux, uy, uz, p = (np.array(a) for a in _uniform_fields((6, 5, 4), (1.0, 0.0, 0.0, 0.0, 1.0)))
+    pr = dict(_params(2.0, 6.0, 2.0, 1.0 / 256), grid=(6, 5, 4))
+    assert lbm3d.lbm3d_admit(pr, (rho, ux, uy, uz, p))[0] == lbm3d.OK
+    rho[2, 3, 1], ux[2, 3, 1], p[2, 3, 1] = rho2, u2, p2
+    assert lbm3d.lbm3d_admit(pr, (rho, ux, uy, uz, p))[0] == lbm3d.E_UNSTABLE
+
+
+def test_admission_checks_fixed_inflow_states():
+    rho2, u2, p2, _ = inputs.rankine_hugoniot(8.0)
+    d = inputs.make_params((8, 8, 8), (2, 1, 0, 0, 0, 0), inflow={0: (rho2, u2, 0.0, 0.0, p2)}, precision="fp64",
+                           c1=2.0, c2=6.0, eta0=2.0)
+    rc, _ = lbm3d.lbm3d_admit(d, _uniform_fields((8, 8, 8), (1.0, 0.0, 0.0, 0.0, 1.0)))
+    assert rc == lbm3d.E_UNSTABLE
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_workload_extremes_are_admitted(seed):
+    """The synthetic workloads' model (8, 24, 8) with dt = tau = 1e-5,
+    dx = 1/256 is admitted at the extremes of every workload: Riemann
+    states down to T = 0.05 and up to T = 100, and Mach-8 shock-bubble
+    set-ups (post-shock u = 7.77, T = 13.4; bubble or droplet)."""
+    for case in (inputs.riemann_3d(seed, grid=(16, 16, 16)),
+                 inputs.shock_bubble(seed, grid=(32, 16, 16), precision="fp64", mach=8.0, ratio=0.1),
+                 inputs.shock_bubble(seed, grid=(32, 16, 16), precision="fp64", mach=8.0, ratio=10.0)):
+        rc, om = lbm3d.lbm3d_admit(case.params, case.fields)
+        assert rc == lbm3d.OK, (case.name, om)
+    extreme = _uniform_fields((4, 4, 4), (2.0, 1.0, 0.0, 0.0, 0.1))  # T = 0.05
+    assert lbm3d.lbm3d_admit(inputs.riemann_3d(0, grid=(4, 4, 4)).params, extreme)[0] == lbm3d.OK
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_collisionless_limit_of_the_upwind2_variant(axis):
+    """With LBM3D_UPWIND2 the convection symbol is the second-order upwind
+    one: without relaxation and dissipation each velocity is advected alone
+    with factor 1 - c (3 - 4 e^{-i theta} + e^{-2 i theta}) / 2 (mirrored
+    for c < 0), which exceeds 1 at long waves for any c > 0: the original
+    scheme is not stable on its own."""
+    c1, c2, dx, dt = 8.0, 24.0, 1.0 / 64, 2e-4
+    p = _params(c1, c2, 8.0, dx, dt=dt, tau=1e6 * dt, flags=1 | 2)
+    cs = [c1 * dt / dx, -c1 * dt / dx, c2 / np.sqrt(3) * dt / dx, -c2 / np.sqrt(3) * dt / dx, 0.0]
+
+    def factor(c, th):
+        e = np.exp(-1j * th)
+        if c >= 0:
+            return abs(1 - c * (3 - 4 * e + e * e) / 2)
+        e = np.exp(1j * th)
+        return abs(1 - c * (-3 + 4 * e - e * e) / 2)
+
+    for th in (0.2, 0.9, 2.0, np.pi):
+        want = max(factor(c, th) for c in cs)
+        got, _ = lbm3d.lbm3d_stability(p, (1.0, 0.0, 0.0, 0.0, 1.0), axis, (th, th), 1)
+        assert abs(got - want) < 1e-4, (th, got, want)
+    assert lbm3d.lbm3d_stability(p, (1.0, 0.0, 0.0, 0.0, 1.0), axis, (0.2, 0.2), 1)[0] > 1.0
