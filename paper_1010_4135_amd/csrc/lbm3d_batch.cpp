@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <set>
 
@@ -428,6 +429,57 @@ extern "C" int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* n
         if (hs[k]->stream != s && hipStreamSynchronize(hs[k]->stream) != hipSuccess) return LBM3D_E_DEVICE;
     BatchPlan plan;
     return batch_advance(hs, count, nsteps, s, plan, nullptr, 0, true);
+}
+
+// ------------------------------------------------ the allocation-free step --
+// The tables of lbm3d_batch_step_noalloc (solve table, tile lists and their
+// counters, boundary-layer jobs, health words) live in this array, one copy
+// per device, held until the process ends.  In host code its name is only a
+// stand-in: the device address of each device's copy comes from
+// hipGetSymbolAddress and is kept per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch;  // device address of `scratch` per device (nullptr: not looked up yet)
+}  // namespace
+
+// The device address of the current device's scratch array (looked up once
+// per device, with that device current).
+static int32_t scratch_address(void** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return LBM3D_E_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((size_t)dev >= g_scratch.size()) g_scratch.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch[(size_t)dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM3D_E_DEVICE;
+        g_scratch[(size_t)dev] = ptr;
+    }
+    *out = g_scratch[(size_t)dev];
+    return LBM3D_OK;
+}
+
+extern "C" int32_t lbm3d_batch_step_noalloc(lbm3d_t* hs, int32_t count, const int64_t* nsteps)
+{
+    int32_t rc = check_batch(hs, count);
+    if (rc) return rc;
+    if (!nsteps) return LBM3D_E_INVAL;
+    for (int32_t k = 0; k < count; k++)
+        if (nsteps[k] < 0) return LBM3D_E_INVAL;
+    std::vector<lbm3d_solver*> members(hs, hs + count);
+    // the full membership needs the largest tables of the call
+    if (BatchPlan::table_bytes(members) > NOALLOC_SCRATCH_BYTES) return LBM3D_E_NOMEM;
+    void* ptr = nullptr;
+    rc = scratch_address(&ptr);
+    if (rc) return rc;
+    hipStream_t s = hs[0]->stream;
+    for (int32_t k = 1; k < count; k++)
+        if (hs[k]->stream != s && hipStreamSynchronize(hs[k]->stream) != hipSuccess) return LBM3D_E_DEVICE;
+    BatchPlan plan;  // tables in the scratch array, steps launched directly (no graph)
+    return batch_advance(hs, count, nsteps, s, plan, ptr, NOALLOC_SCRATCH_BYTES, false);
 }
 
 extern "C" int32_t lbm3d_batch_plan(const lbm3d_params* ps, int32_t count, int32_t tz, int32_t cus,

@@ -94,6 +94,7 @@ def _load():
         "lbm3d_poison_next": (I32, [P]),
         "lbm3d_set_f": (I32, [P, P, SZ]),
         "lbm3d_batch_step": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(I64)]),
+        "lbm3d_batch_step_noalloc": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(I64)]),
         "lbm3d_batch_plan": (I32, [PP, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
                                    ctypes.POINTER(I32), I64, ctypes.POINTER(I32)]),
         "lbm3d_server_create": (I32, [SZ, I32, ctypes.POINTER(P)]),
@@ -317,6 +318,12 @@ def lbm3d_batch_step(handles, nsteps):
     arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
     ns = (ctypes.c_int64 * len(handles))(*[int(n) for n in nsteps])
     _check(_lib.lbm3d_batch_step(arr, len(handles), ns), "lbm3d_batch_step")
+
+
+def lbm3d_batch_step_noalloc(handles, nsteps):
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    ns = (ctypes.c_int64 * len(handles))(*[int(n) for n in nsteps])
+    _check(_lib.lbm3d_batch_step_noalloc(arr, len(handles), ns), "lbm3d_batch_step_noalloc")
 
 
 def lbm3d_batch_set_depth(precision, tz: int):
