@@ -4,7 +4,8 @@
 Headline (`value`): MLUPS of the time step on the 256x128x128 shock-bubble
 problem (planar shock of seeded Mach number into quiescent gas, a bubble or
 droplet of seeded density ratio, inflow/outflow in x, reflecting walls in y
-and z), FP32 storage and arithmetic with the temperature recovered in FP64,
+and z), FP32 storage and bulk arithmetic with the moments, temperature and
+equilibrium in FP64,
 synthetic seeded input already resident on the device.  A step is one time
 step of the whole grid: the fused moments + equilibrium + NND convection +
 dissipation + BGK update kernel and the boundary-layer kernel, replayed from
@@ -19,24 +20,30 @@ Beside it:
                 kernel source, else null;
   copy_ceiling  the rate of a plain copy of the same bytes between two
                 alternating buffers, the practical ceiling of such a kernel;
-  periodic_riemann  the 128^3 periodic 3D Riemann problem in FP64, FP32 and
-                FP32 with FP64 temperature: MLUPS, kernel GB/s and the FP32
-                modes' error against the FP64 run;
+  accuracy_2000_steps  the headline problem over its full 2000 steps in
+                FP64, FP32 with FP64 moments and equilibrium, and FP32: the
+                FP32 modes' per-field error against the FP64 run;
+  periodic_riemann  the 128^3 periodic 3D Riemann problem over its 1000
+                steps in FP64, FP32 and FP32 with FP64 moments and
+                equilibrium: MLUPS, kernel GB/s and the FP32 modes' error
+                against the FP64 run;
   batch         64 solves of uneven size, 500 steps each, in one persistent
                 launch per step vs the same solves stepped one after another,
                 and vs the plain one-at-a-time FP64 loop (with the batched
                 results' error against it);
-  serving       an open Poisson stream of mixed solves through the
+  serving       an open Poisson stream of 200 mixed solves through the
                 continuous-batching server vs the plain one-at-a-time FP64
-                loop on the same arrival times: solves/s, p50/p99 time to
-                solution, and the served results' error against FP64, at
-                50%, 80% and 95% of the served capacity (top-level figures:
+                loop: capacities and their ratio, and at 50%, 80% and 95% of
+                the served capacity solves/s, p50/p99 time to solution
+                (overall and per grid size), the server's tick counters and
+                the served results' error against FP64 (top-level figures:
                 80%);
-  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample.
+  cpu_baseline  the FP64 oracle on the host cores (model, clock, count
+                stated), median of three timings on a bounded sample.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S]
                   [--no-batch] [--no-serve] [--no-cpu-baseline] [--copy-check]
-                  [--batch-only]
+                  [--batch-only] [--serve-requests N]
 """
 from __future__ import annotations
 
@@ -46,7 +53,6 @@ import json
 import os
 import re
 import sys
-import threading
 import time
 
 import numpy as np
@@ -91,27 +97,78 @@ def measured_traffic(precision: str):
         return None
 
 
-def cpu_baseline(case, steps: int = 3):
-    """The FP64 oracle on the host cores, on the same grid for a few steps."""
+def host_cpu():
+    """Model, clock and core counts of the host this runs on."""
+    model, mhz = "unknown", None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name") and model == "unknown":
+                model = line.split(":", 1)[1].strip()
+            elif line.startswith("cpu MHz") and mhz is None:
+                mhz = float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpu_mhz": mhz, "nproc": os.cpu_count(),
+            "affinity_cores": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(case, steps: int = 3, reps: int = 3):
+    """The FP64 oracle on the host cores this process may use (its CPU
+    affinity, capped by OMP_NUM_THREADS when set), on the same grid: one
+    warm-up step, then `reps` timings of `steps` steps, median; and the same
+    oracle on one thread (median of `reps` single steps)."""
     import oracle
 
-    threads = min(16, len(os.sched_getaffinity(0)))
+    threads = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
     used = oracle.set_threads(threads)
     o = oracle.Oracle(case.params)
     o.init(*case.fields)
     o.step(1)  # warm-up
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    # the same oracle on one thread, one step
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        o.step(steps)
+        times.append(time.perf_counter() - t0)
     oracle.set_threads(1)
-    t0 = time.perf_counter()
-    o.step(1)
-    dt1 = time.perf_counter() - t0
+    times1 = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        o.step(1)
+        times1.append(time.perf_counter() - t0)
     oracle.set_threads(used)
-    return {"value": round(case.sites * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": used, "kind": "oracle",
-            "sample": f"{case.grid[0]}x{case.grid[1]}x{case.grid[2]} full grid, {steps} steps after 1 warm-up, FP64",
-            "single_thread_value": round(case.sites / dt1 / 1e6, 3)}
+    out = {"value": round(case.sites * steps / float(np.median(times)) / 1e6, 3), "unit": "MLUPS", "cores": used,
+           "kind": "oracle",
+           "sample": f"{case.grid[0]}x{case.grid[1]}x{case.grid[2]} full grid, FP64, 1 warm-up step then "
+                     f"{steps} steps timed {reps} times (median)",
+           "single_thread_value": round(case.sites / float(np.median(times1)) / 1e6, 3),
+           "timings_s": [round(t, 3) for t in times]}
+    out.update(host_cpu())
+    return out
+
+
+def accuracy_full_length(lbm3d, inputs, metrics, seed: int, steps: int = 2000):
+    """The headline problem run for its full 2000 steps in FP64, FP32 with
+    FP64 moments and equilibrium, and plain FP32: per-field relative L1
+    distance of the FP32 modes to the FP64 run (the FP64 mode itself is held
+    to the FP64 oracle by the parity tests), health of each run."""
+    case = inputs.shock_bubble(seed, precision="fp64")
+    ref = None
+    out = {"workload": f"shock_bubble {case.grid[0]}x{case.grid[1]}x{case.grid[2]}", "steps": steps}
+    for prec in ("fp64", "fp32_t64", "fp32"):
+        with lbm3d.Solver(dict(case.params, precision=prec)) as s:
+            s.init(*case.fields)
+            s.step(steps)
+            m = s.moments(allow_nonfinite=True)
+            health, _ = s.status()
+        row = {"health": health}
+        if prec == "fp64":
+            ref = m
+        else:
+            row["rel_l1_vs_fp64"] = {k: float(f"{v:.3e}") for k, v in metrics.rel_l1(m, ref).items()}
+        out[prec] = row
+    return out
 
 
 def batch_bench(lbm3d, inputs, metrics, seed: int, count: int = 64, steps: int = 500):
@@ -174,7 +231,7 @@ def batch_bench(lbm3d, inputs, metrics, seed: int, count: int = 64, steps: int =
             "max_rel_l1_batched_vs_fp64": float(f"{err:.3e}")}
 
 
-def periodic_riemann_bench(lbm3d, inputs, metrics, seed: int, steps: int = 200):
+def periodic_riemann_bench(lbm3d, inputs, metrics, seed: int, steps: int = 1000):
     """128^3 periodic 3D Riemann problem in each precision: MLUPS, the step
     kernel's algorithmic GB/s, and the FP32 modes' per-field relative L1
     distance to the FP64 run after the same steps (the FP64 mode itself is
@@ -205,68 +262,96 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v), q)) if len(v) else None
 
 
-def serve_bench(lbm3d, inputs, metrics, seed: int, count: int = 24):
-    """Open Poisson stream: served (continuous batching, FP32 + FP64 T) vs the
-    plain one-at-a-time FP64 loop on the same arrival times."""
-    # capacity of the served path with everything submitted at once sets the rate
-    probe = inputs.serve_trace(seed + 1, count=count, rate=1e9)
+def serve_bench(lbm3d, inputs, metrics, seed: int, count: int = 200):
+    """Open Poisson stream of `count` mixed solves (one draw of requests for
+    every load level; only the arrival times scale with the rate).
+
+    - served capacity: every request submitted at once to the
+      continuous-batching server (FP32 with FP64 moments and equilibrium);
+    - baseline: the plain one-at-a-time FP64 loop over the same requests
+      back to back (create, init, step, read back, free), which gives each
+      request's service time, the FP64 results and the baseline capacity;
+    - at 50%, 80% and 95% of the served capacity: the served path on the
+      open stream, measured; the baseline's latencies are its measured
+      service times replayed through the FIFO queue of the same arrival
+      times (the loop serves one request at a time, so that replay is its
+      schedule).  p50/p99 time to solution overall and per grid size,
+      solves/s, and the server's tick counters."""
+    base_trace = inputs.serve_trace(seed, count=count, rate=1.0)
     budget = int(200e9)
 
-    def run_served(trace):
+    def served(rate):
         with lbm3d.Server(budget, 64, tick_steps=32) as srv:
             t_start = time.perf_counter()
             tickets = []
-            for t_arr, c in trace:
-                delay = t_arr - (time.perf_counter() - t_start)
+            for t_arr, c in base_trace:
+                delay = t_arr / rate - (time.perf_counter() - t_start)
                 if delay > 0:
                     time.sleep(delay)
                 tickets.append((srv.submit(c.params, c.fields, c.steps), c))
-            out, lat = [], []
+            res, lat = [], []
             for t, c in tickets:
                 nx, ny, nz = c.grid
                 rc, fields, tm = srv.wait(t, (nz, ny, nx))
-                out.append(fields)
+                res.append(fields)
                 lat.append(tm["t_done"] - tm["t_submit"])
             wall = time.perf_counter() - t_start
-        return out, lat, wall
+            st = srv.stats()
+        return res, lat, wall, st
 
-    def run_base(trace):
-        # each request alone in FP64, in arrival order
-        base, lat = [], []
-        t_start = time.perf_counter()
-        for t_arr, c in trace:
-            now = time.perf_counter() - t_start
-            if t_arr > now:
-                time.sleep(t_arr - now)
-            prm = dict(c.params, precision="fp64")
-            s = lbm3d.Solver(prm)
+    # baseline: FP64, one request at a time, back to back
+    service, base = [], []
+    for _, c in base_trace:
+        t0 = time.perf_counter()
+        with lbm3d.Solver(dict(c.params, precision="fp64")) as s:
             s.init(*c.fields)
             s.step(c.steps)
             base.append(s.moments())
-            s.close()
-            lat.append(time.perf_counter() - t_start - t_arr)
-        return base, lat, time.perf_counter() - t_start
-
-    _, _, w = run_served(probe)
-    capacity = count / w
+        service.append(time.perf_counter() - t0)
+    base_capacity = count / sum(service)
+    _, _, w_cap, st_cap = served(1e12)
+    capacity = count / w_cap
     out = {"requests": count, "served_precision": "fp32_t64",
-           "baseline": "one solve at a time, FP64, arrival order"}
+           "baseline": "one solve at a time, FP64, arrival order; latencies from its measured service times "
+                       "replayed through the FIFO queue of the arrival trace",
+           "served_capacity_solves_per_s": round(capacity, 3),
+           "baseline_capacity_solves_per_s": round(base_capacity, 3),
+           "capacity_ratio": round(capacity / base_capacity, 3),
+           "capacity_run_busy_frac": round(st_cap["busy_s"] / max(w_cap, 1e-9), 3)}
+    grids = sorted({c.grid for _, c in base_trace})
     levels = []
-    # the same requests (one seed) arriving at 50%, 80% and 95% of the
-    # served capacity; the headline figures are those at 80%
     for load in (0.5, 0.8, 0.95):
         rate = load * capacity
-        trace = inputs.serve_trace(seed, count=count, rate=rate)
-        served, lat_s, wall_s = run_served(trace)
-        base, lat_b, wall_b = run_base(trace)
+        res, lat_s, wall_s, st = served(rate)
+        arr = [t / rate for t, _ in base_trace]
+        lat_b, fin = [], 0.0
+        for a, sv in zip(arr, service):
+            fin = max(a, fin) + sv
+            lat_b.append(fin - a)
+        wall_b = fin
+        err = max(metrics.max_rel_l1(a, b) for a, b in zip(res, base))
         row = {"load": load, "arrival_rate_per_s": round(rate, 3),
                "served_solves_per_s": round(count / wall_s, 3), "baseline_solves_per_s": round(count / wall_b, 3),
                "throughput_ratio": round(wall_b / wall_s, 3),
                "served_p50_s": round(_pct(lat_s, 50), 4), "served_p99_s": round(_pct(lat_s, 99), 4),
                "baseline_p50_s": round(_pct(lat_b, 50), 4), "baseline_p99_s": round(_pct(lat_b, 99), 4),
-               "max_rel_l1_served_vs_fp64": float(f"{max(metrics.max_rel_l1(a, b) for a, b in zip(served, base)):.3e}")}
+               "max_rel_l1_served_vs_fp64": float(f"{err:.3e}"),
+               "server": {"ticks": st["ticks"], "rebuilds": st["rebuilds"], "evicted": st["evicted"],
+                          "busy_frac": round(st["busy_s"] / max(st["wall_s"], 1e-9), 3),
+                          "plan_s": round(st["plan_s"], 3), "admit_s": round(st["admit_s"], 3),
+                          "finish_s": round(st["finish_s"], 3)}}
+        by_grid = {}
+        for g in grids:
+            idx = [k for k, (_, c) in enumerate(base_trace) if c.grid == g]
+            by_grid["x".join(map(str, g))] = {
+                "n": len(idx),
+                "served_p50_s": round(_pct([lat_s[k] for k in idx], 50), 4),
+                "served_p99_s": round(_pct([lat_s[k] for k in idx], 99), 4),
+                "baseline_p50_s": round(_pct([lat_b[k] for k in idx], 50), 4),
+                "baseline_p99_s": round(_pct([lat_b[k] for k in idx], 99), 4)}
+        row["by_grid"] = by_grid
         if load == 0.8:
-            out.update({k: v for k, v in row.items() if k != "load"})
+            out.update({k: v for k, v in row.items() if k not in ("load", "by_grid")})
         levels.append(row)
     out["by_load"] = levels
     return out
@@ -284,6 +369,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run the checkpoint pack (a plain copy of 15 x nodes elements) for counter calibration")
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched step of the 64-solve mix (--steps steps) and print its rate")
     args = ap.parse_args()
@@ -324,6 +410,11 @@ def main():
     s.tune(10)
     t_tune = time.perf_counter() - t_tune
     s.step(args.warmup)
+    # runs of 32 steps replay a captured graph: capture it here, outside the
+    # timed region (the state advances 32 more steps, untimed)
+    graph_prep = 32 if args.steps >= 32 else 0
+    if graph_prep:
+        s.step(graph_prep)
     s.sync()
     # timed region: K steps replayed from captured graphs, HIP events on the
     # solver's stream, host clock around it
@@ -356,10 +447,12 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"shock_bubble {nx}x{ny}x{nz}, {args.precision}" +
-                        (" (FP32 f, FP64 temperature recovery)" if args.precision == "fp32_t64" else ""),
+                        (" (FP32 f, FP64 moments, temperature and equilibrium)" if args.precision == "fp32_t64"
+                         else ""),
             "grid": [nx, ny, nz], "precision": args.precision, "seed": args.seed,
             "mach": round(case.meta["mach"], 4), "density_ratio": round(case.meta["ratio"], 4),
             "tile": [64, by, tz], "tile_from": "autotuner", "tune_s": round(t_tune, 3),
+            "graph_capture_steps": graph_prep,
             "wall_s_timed_region": round(wall, 4), "health": health, "steps_done": done,
         },
         "roofline": {
@@ -379,10 +472,11 @@ def main():
         "step_kernel_frac_of_copy": round(achieved / copy_gbs, 4),
     }
     if not args.no_batch:
-        out["periodic_riemann"] = periodic_riemann_bench(lbm3d, inputs, metrics, args.seed)
+        out["accuracy_2000_steps"] = accuracy_full_length(lbm3d, inputs, metrics, args.seed)
+        out["periodic_riemann"] = periodic_riemann_bench(lbm3d, inputs, metrics, args.seed, steps=1000)
         out["batch"] = batch_bench(lbm3d, inputs, metrics, args.seed)
     if not args.no_serve:
-        out["serving"] = serve_bench(lbm3d, inputs, metrics, args.seed)
+        out["serving"] = serve_bench(lbm3d, inputs, metrics, args.seed, count=args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)
