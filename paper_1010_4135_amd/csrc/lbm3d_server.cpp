@@ -54,7 +54,8 @@ struct lbm3d_server {
     bool stop = false;
     bool membership_changed = true;
     std::thread worker;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the ticks
+    hipStream_t side = nullptr;    // initialisation and read-back of solves outside the running tick
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     lbm3d::BatchPlan plans[3];  // one per precision
     lbm3d_server_counters stats{};  // guarded by mu
@@ -86,18 +87,21 @@ void lbm3d_server::finish(Ticket* t, int32_t status)
     t->status = status;
     t->t_done = now();
     t->state = Ticket::DONE;
-    membership_changed = true;
     cv_done.notify_all();
 }
 
 void lbm3d_server::run()
 {
     (void)hipSetDevice(device);
-    using lbm3d::BatchPlan;
     auto secs = [](Clock::time_point a) { return std::chrono::duration<double>(Clock::now() - a).count(); };
+    // Solves that finished at the last tick (done, failed, evicted or
+    // cancelled) with their status: read back and freed while the next tick
+    // runs.  Their memory stays counted against the budget until then.
+    std::vector<std::pair<Ticket*, int32_t>> finishing;
     for (;;) {
         std::vector<Ticket*> admit;
-        std::vector<Ticket*> cancelled;
+        std::vector<Ticket*> act;
+        bool rebuild = false;
         {
             std::unique_lock<std::mutex> lk(mu);
             for (;;) {
@@ -122,26 +126,75 @@ void lbm3d_server::run()
                     used += t->footprint;
                     admit.push_back(t);
                 }
-                for (Ticket* t : active)
-                    if (t->cancel) cancelled.push_back(t);
-                if (!admit.empty() || !active.empty() || stop) break;
+                // running tickets that were cancelled leave the active set
+                for (auto it = active.begin(); it != active.end();) {
+                    if ((*it)->cancel) {
+                        finishing.emplace_back(*it, LBM3D_E_CANCELLED);
+                        it = active.erase(it);
+                        membership_changed = true;
+                    } else {
+                        ++it;
+                    }
+                }
+                if (!admit.empty() || !active.empty() || !finishing.empty() || stop) break;
                 cv_work.wait(lk);
             }
-            if (stop && admit.empty() && active.empty()) return;
+            if (stop && admit.empty() && active.empty() && finishing.empty()) return;
+            act = active;
+            rebuild = membership_changed;
+            membership_changed = false;
         }
-        // new solves: allocate and initialise outside the lock
+        // 1. one tick of the active solves, enqueued without waiting: every
+        // precision group advances by the same number of steps, at most
+        // tick_steps and at most what its members still need.  A plan
+        // rebuilt for a new membership runs its first tick with direct
+        // launches; a graph is captured only for a membership that has
+        // lasted a tick (its replays then pay for the capture).
+        int32_t err = LBM3D_OK;
+        double plan_s = 0.0;
+        int rebuilds = 0;
+        std::vector<Ticket*> members_of[3];
+        const bool ticking = !act.empty();
+        if (ticking) {
+            (void)hipEventRecord(ev0, stream);
+            for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++) {
+                std::vector<lbm3d_solver*> members;
+                int64_t k = tick_steps;
+                for (Ticket* t : act)
+                    if (t->h->mode == mode) {
+                        members.push_back(t->h);
+                        members_of[mode].push_back(t);
+                        k = std::min(k, t->left);
+                    }
+                if (members.empty() || k <= 0) continue;
+                const bool fresh = rebuild || plans[mode].ntiles() == 0;
+                if (fresh) {
+                    const auto tp = Clock::now();
+                    err = plans[mode].build(members, stream);
+                    plan_s += secs(tp);
+                    rebuilds++;
+                }
+                if (err == LBM3D_OK) err = plans[mode].run(k, stream, !fresh);
+                if (err == LBM3D_OK)
+                    for (Ticket* t : members_of[mode]) t->left -= k;
+            }
+            (void)hipEventRecord(ev1, stream);
+        }
+        // 2. while the tick runs: allocate and initialise the admitted solves
+        // on the side stream (they join the next tick)
         const auto ta = Clock::now();
+        int nadmit = 0;
         for (Ticket* t : admit) {
             lbm3d_solver* h = nullptr;
             int32_t rc = lbm3d_create(&t->p, &h);
-            if (rc == LBM3D_OK) rc = lbm3d_set_stream(h, stream);
+            if (rc == LBM3D_OK) rc = lbm3d_set_stream(h, side);
             if (rc == LBM3D_OK)
                 rc = lbm3d_init(h, t->in[0].data(), t->in[1].data(), t->in[2].data(), t->in[3].data(),
                                 t->in[4].data());
             for (auto& v : t->in) std::vector<double>().swap(v);
             t->h = h;
             if (rc != LBM3D_OK) {
-                finish(t, rc);
+                finishing.emplace_back(t, rc);
                 continue;
             }
             std::lock_guard<std::mutex> lk(mu);
@@ -149,94 +202,53 @@ void lbm3d_server::run()
             t->state = Ticket::ACTIVE;
             active.push_back(t);
             membership_changed = true;
-            stats.admitted++;
+            nadmit++;
         }
         const double admit_s = admit.empty() ? 0.0 : secs(ta);
-        // evict cancelled solves
-        for (Ticket* t : cancelled) {
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                active.erase(std::find(active.begin(), active.end(), t));
-            }
-            finish(t, LBM3D_E_CANCELLED);
-        }
-        std::vector<Ticket*> act;
-        bool rebuild;
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            act = active;
-            rebuild = membership_changed;
-            membership_changed = false;
-            stats.admit_s += admit_s;
-        }
-        if (act.empty()) continue;
-        // one tick: every precision group advances by the same number of
-        // steps, at most tick_steps and at most what its members still need.
-        // A plan rebuilt for a new membership runs its first tick with
-        // direct launches; a graph is captured only for a membership that
-        // has lasted a tick (its replays then pay for the capture).
-        int32_t err = LBM3D_OK;
-        double plan_s = 0.0;
-        int rebuilds = 0;
-        std::vector<Ticket*> members_of[3];
-        (void)hipEventRecord(ev0, stream);
-        for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++) {
-            std::vector<lbm3d_solver*> members;
-            int64_t k = tick_steps;
-            for (Ticket* t : act)
-                if (t->h->mode == mode) {
-                    members.push_back(t->h);
-                    members_of[mode].push_back(t);
-                    k = std::min(k, t->left);
-                }
-            if (members.empty() || k <= 0) continue;
-            const bool fresh = rebuild || plans[mode].ntiles() == 0;
-            if (fresh) {
-                const auto tp = Clock::now();
-                err = plans[mode].build(members, stream);
-                plan_s += secs(tp);
-                rebuilds++;
-            }
-            if (err == LBM3D_OK) err = plans[mode].run(k, stream, !fresh);
-            if (err == LBM3D_OK)
-                for (Ticket* t : members_of[mode]) t->left -= k;
-        }
-        (void)hipEventRecord(ev1, stream);
-        if (err == LBM3D_OK && hipStreamSynchronize(stream) != hipSuccess) err = LBM3D_E_DEVICE;
-        float busy_ms = 0.0f;
-        if (err == LBM3D_OK) (void)hipEventElapsedTime(&busy_ms, ev0, ev1);
-        // health of every member after the tick (one gather per precision):
-        // a solve that has gone non-finite stops now instead of running out
-        // its steps
-        std::vector<uint32_t> hw_of[3];
-        for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++)
-            if (!members_of[mode].empty()) err = plans[mode].health(hw_of[mode], stream);
-        // completions (and every active solve if the tick failed)
+        // 3. while the tick runs: read back and free the solves that finished
+        // at the previous tick (read-back on the side stream; freeing waits
+        // for the device)
         const auto tf = Clock::now();
-        int ndone = 0, nevict = 0;
-        for (int mode = 0; mode < 3; mode++) {
-            for (size_t j = 0; j < members_of[mode].size(); j++) {
-                Ticket* t = members_of[mode][j];
-                const uint32_t hw = (err == LBM3D_OK && j < hw_of[mode].size()) ? hw_of[mode][j] : 0u;
-                const bool bad = (hw & LBM3D_HEALTH_NONFINITE) != 0;
-                if (err == LBM3D_OK && t->left > 0 && !bad) continue;
-                {
-                    std::lock_guard<std::mutex> lk(mu);
-                    active.erase(std::find(active.begin(), active.end(), t));
+        const size_t nfinish = finishing.size();
+        for (auto& ts : finishing) finish(ts.first, ts.second);
+        finishing.clear();
+        const double finish_s = nfinish ? secs(tf) : 0.0;
+        // 4. wait for the tick, then the health of every member (one gather
+        // per precision): a solve that has gone non-finite stops now instead
+        // of running out its steps
+        float busy_ms = 0.0f;
+        int nevict = 0;
+        if (ticking) {
+            if (err == LBM3D_OK && hipStreamSynchronize(stream) != hipSuccess) err = LBM3D_E_DEVICE;
+            if (err == LBM3D_OK) (void)hipEventElapsedTime(&busy_ms, ev0, ev1);
+            std::vector<uint32_t> hw_of[3];
+            for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++)
+                if (!members_of[mode].empty()) err = plans[mode].health(hw_of[mode], stream);
+            std::lock_guard<std::mutex> lk(mu);
+            for (int mode = 0; mode < 3; mode++) {
+                for (size_t j = 0; j < members_of[mode].size(); j++) {
+                    Ticket* t = members_of[mode][j];
+                    const uint32_t hw = (err == LBM3D_OK && j < hw_of[mode].size()) ? hw_of[mode][j] : 0u;
+                    const bool bad = (hw & LBM3D_HEALTH_NONFINITE) != 0;
+                    if (err == LBM3D_OK && t->left > 0 && !bad) continue;
+                    auto it = std::find(active.begin(), active.end(), t);
+                    if (it != active.end()) active.erase(it);
+                    membership_changed = true;
+                    if (bad && t->left > 0) nevict++;
+                    finishing.emplace_back(t, err != LBM3D_OK ? err : (bad ? LBM3D_E_NONFINITE : LBM3D_OK));
                 }
-                if (bad && t->left > 0) nevict++;
-                ndone++;
-                finish(t, err != LBM3D_OK ? err : (bad ? LBM3D_E_NONFINITE : LBM3D_OK));
             }
         }
         std::lock_guard<std::mutex> lk(mu);
-        stats.ticks++;
+        if (ticking) stats.ticks++;
         stats.rebuilds += rebuilds;
         stats.plan_s += plan_s;
         stats.busy_s += busy_ms * 1e-3;
-        stats.completed += ndone;
+        stats.admitted += nadmit;
+        stats.completed += (int64_t)nfinish;
         stats.evicted += nevict;
-        if (ndone) stats.finish_s += secs(tf);
+        stats.admit_s += admit_s;
+        stats.finish_s += finish_s;
     }
 }
 
@@ -253,8 +265,10 @@ int32_t lbm3d_server_create(size_t hbm_budget_bytes, int32_t max_active, lbm3d_s
     s->t0 = Clock::now();
     if (hipGetDevice(&s->device) != hipSuccess ||
         hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess) {
         if (s->ev0) (void)hipEventDestroy(s->ev0);
+        if (s->side) (void)hipStreamDestroy(s->side);
         if (s->stream) (void)hipStreamDestroy(s->stream);
         delete s;
         return LBM3D_E_DEVICE;
@@ -264,6 +278,7 @@ int32_t lbm3d_server_create(size_t hbm_budget_bytes, int32_t max_active, lbm3d_s
     } catch (...) {
         (void)hipEventDestroy(s->ev0);
         (void)hipEventDestroy(s->ev1);
+        (void)hipStreamDestroy(s->side);
         (void)hipStreamDestroy(s->stream);
         delete s;
         return LBM3D_E_NOMEM;
@@ -389,9 +404,11 @@ int32_t lbm3d_server_destroy(lbm3d_server_t s)
     }
     if (s->worker.joinable()) s->worker.join();
     (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->side);
     for (auto& pl : s->plans) pl.build({}, s->stream);  // drop the plans' graphs and tables first
     (void)hipEventDestroy(s->ev0);
     (void)hipEventDestroy(s->ev1);
+    (void)hipStreamDestroy(s->side);
     (void)hipStreamDestroy(s->stream);
     delete s;
     return LBM3D_OK;

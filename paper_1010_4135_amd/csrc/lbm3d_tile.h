@@ -179,7 +179,6 @@ __device__ __forceinline__ void layer_line(const StepArgs<MODE>& A, const Model<
                                            const Model<typename Types<MODE>::C>& mc, int face, uint32_t line,
                                            uint32_t st, int n, uint32_t l1, uint32_t l2)
 {
-    using S = typename Types<MODE>::S;
     using C = typename Types<MODE>::C;
     using M = typename Types<MODE>::M;
     const int64_t sv = A.g.sv;
