@@ -136,8 +136,15 @@ int32_t lbm3d_init(lbm3d_t h, const double* rho, const double* ux, const double*
                    const double* uz, const double* p);
 
 /* Enqueue nsteps explicit time steps (asynchronous on the handle's stream;
- * runs of steps are replayed from a captured HIP graph).  E_STATE before
- * init; nsteps >= 0. */
+ * runs of steps are replayed from a captured HIP graph).  One step is
+ * Sec. 3, Eq. (fi1) applied to Eq. (lp): at every interior node
+ *   f_i <- f_i - dt/dx sum_a (h_{I+1/2} - h_{I-1/2})_ia - dt/tau (f_i - f_i^eq)
+ *          + lambda_i dt/dx^2 sum_a (f_{I+1} - 2 f_I + f_{I-1})_a,
+ * the convection by the NND fluxes of Eq. (nnd) (or the second-order upwind
+ * difference with LBM3D_UPWIND2), f^eq of Eqs. (eq)/(e18) from the moments
+ * of Eqs. (e1)-(e3), every term at the old level; then the boundary layers
+ * of Sec. 4 (2) are refreshed for the new level.  E_STATE before init;
+ * E_INVAL for nsteps < 0. */
 int32_t lbm3d_step(lbm3d_t h, int64_t nsteps);
 
 /* As lbm3d_step, then wait; *ms receives the device time of the steps
@@ -214,14 +221,19 @@ int32_t lbm3d_admit(const lbm3d_params* p, const double* rho, const double* ux, 
 int32_t lbm3d_stream_copy_rate(int64_t bytes, int32_t launches, double* gbs);
 
 /* (rho, u, p = rho T) on the interior nodes into caller arrays of nx*ny*nz
- * doubles each (any pointer may be NULL to skip that field).  Blocking.
- * Returns E_NONFINITE (after filling the arrays) if the health word has the
- * NONFINITE bit. */
+ * doubles each (any pointer may be NULL to skip that field): the moments of
+ * Sec. 2, Eqs. (e1)-(e3), applied to f (rho = sum f, rho u = sum f v,
+ * rho (b T + u^2) = sum f (v^2 + eta^2)), in FP64 in the FP64 and FP32_T64
+ * modes.  Blocking.  Returns E_NONFINITE (after filling the arrays) if the
+ * health word has the NONFINITE bit; E_STATE before init. */
 int32_t lbm3d_moments(lbm3d_t h, double* rho, double* ux, double* uy, double* uz, double* p);
 
-/* Domain totals over the interior nodes, accumulated in FP64 with a fixed
+/* Domain totals over the interior nodes of the densities the scheme
+ * conserves (Sec. 2, Eqs. (e1)-(e3): the collision invariants 1, v and
+ * (v^2 + eta^2)/2 summed against f), accumulated in FP64 with a fixed
  * reduction order (bitwise reproducible): out[0] mass sum rho, out[1..3]
- * momentum sum rho u, out[4] energy sum rho (b T + u^2)/2.  Blocking. */
+ * momentum sum rho u, out[4] energy sum rho (b T + u^2)/2.  On periodic
+ * boxes they are conserved to rounding.  Blocking; E_STATE before init. */
 int32_t lbm3d_conserved(lbm3d_t h, double out[5]);
 
 /* Health bits (LBM3D_HEALTH_*) accumulated since init, and steps done. */
