@@ -175,6 +175,24 @@ int32_t lbm3d_get_tile(lbm3d_t h, int32_t* by, int32_t* tz);
  * the shape.  E_STATE before lbm3d_init. */
 int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t* tz);
 
+/* On-disk cache of the autotuner's results (the tile shape per precision,
+ * grid and boundary kinds, and the batch tile depth per precision), so that
+ * a later process starts with the tuned shapes without tuning again.  The
+ * file is text: a header "lbm3d-tune 1 <arch>" naming the GPU architecture
+ * (gcnArchName, "none" without a device) the shapes were timed on, then
+ * lines "tile <precision> <nx> <ny> <nz> <six boundary kinds> <by> <tz>" and
+ * "batch <precision> <tz>".
+ * lbm3d_tune_save writes every result of this process (atomically: a
+ * temporary file renamed over `path`); E_INVAL if it cannot be written.
+ * lbm3d_tune_load merges a file's results into this process's: E_NOTFOUND
+ * if it cannot be opened, E_INVAL (and nothing merged) if it is not such a
+ * file, was written for another architecture, or holds a bad line.
+ * With the environment variable LBM3D_TUNE_CACHE set to a path, that file is
+ * loaded (errors ignored) before the first lookup of the process, and saved
+ * after every lbm3d_tune and lbm3d_batch_tune. */
+int32_t lbm3d_tune_save(const char* path);
+int32_t lbm3d_tune_load(const char* path);
+
 /* Wait for all work enqueued on the handle's stream. */
 int32_t lbm3d_sync(lbm3d_t h);
 

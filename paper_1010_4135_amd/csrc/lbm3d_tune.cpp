@@ -9,9 +9,13 @@
 
 #include <algorithm>
 #include <array>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <set>
+#include <string>
 #include <vector>
 
 namespace lbm3d {
@@ -53,11 +57,97 @@ std::vector<TileCfg> tile_candidates(int mode, const Grid& g)
     return c;
 }
 
+// ---- on-disk cache of the results ----
+// Text file: a header "lbm3d-tune 1 <arch>" naming the device architecture
+// the shapes were measured on, then one line per result:
+//   tile <precision> <nx> <ny> <nz> <bc -x> <bc +x> <bc -y> <bc +y> <bc -z> <bc +z> <by> <tz>
+//   batch <precision> <tz>
+
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "none";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+int32_t save_locked(const char* path)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return LBM3D_E_INVAL;
+    bool ok = std::fprintf(fp, "lbm3d-tune 1 %s\n", device_arch().c_str()) > 0;
+    for (const auto& kv : g_tiles) {
+        const auto& v = kv.first.v;
+        ok = ok && std::fprintf(fp, "tile %d %d %d %d %d %d %d %d %d %d %d %d\n", v[0], v[1], v[2], v[3], v[4], v[5],
+                                v[6], v[7], v[8], v[9], kv.second.by, kv.second.tz) > 0;
+    }
+    for (int m = 0; m < 3; m++)
+        if (g_batch_tz[m] > 0) ok = ok && std::fprintf(fp, "batch %d %d\n", m, g_batch_tz[m]) > 0;
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return LBM3D_E_INVAL;
+    }
+    return LBM3D_OK;
+}
+
+int32_t load_locked(const char* path)
+{
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return LBM3D_E_NOTFOUND;
+    std::map<ShapeKey, TileCfg> tiles;
+    int batch[3] = {0, 0, 0};
+    char line[512], kind[16], arch[128];
+    int version = 0;
+    bool ok = std::fgets(line, sizeof line, fp) && std::sscanf(line, "lbm3d-tune %d %127s", &version, arch) == 2 &&
+              version == 1 && device_arch() == arch;
+    while (ok && std::fgets(line, sizeof line, fp)) {
+        if (std::sscanf(line, "%15s", kind) != 1) continue;  // blank line
+        if (!std::strcmp(kind, "tile")) {
+            ShapeKey k;
+            TileCfg t;
+            ok = std::sscanf(line, "tile %d %d %d %d %d %d %d %d %d %d %d %d", &k.v[0], &k.v[1], &k.v[2], &k.v[3],
+                             &k.v[4], &k.v[5], &k.v[6], &k.v[7], &k.v[8], &k.v[9], &t.by, &t.tz) == 12;
+            ok = ok && k.v[0] >= 0 && k.v[0] <= 2 && k.v[1] >= 1 && k.v[2] >= 1 && k.v[3] >= 1;
+            for (int f = 4; ok && f < 10; f++) ok = k.v[f] >= LBM3D_PERIODIC && k.v[f] <= LBM3D_REFLECT;
+            ok = ok && (t.by == 0 || t.by == 2 || t.by == 4 || (t.by == 8 && k.v[0] != 0)) && t.tz >= 1 && t.tz <= 65535;
+            if (ok) tiles[k] = t;
+        } else if (!std::strcmp(kind, "batch")) {
+            int m = -1, tz = 0;
+            ok = std::sscanf(line, "batch %d %d", &m, &tz) == 2 && m >= 0 && m <= 2 && tz >= 1 && tz <= 65535;
+            if (ok) batch[m] = tz;
+        } else {
+            ok = false;
+        }
+    }
+    std::fclose(fp);
+    if (!ok) return LBM3D_E_INVAL;  // nothing merged from a bad file
+    for (const auto& kv : tiles) g_tiles[kv.first] = kv.second;
+    for (int m = 0; m < 3; m++)
+        if (batch[m] > 0) g_batch_tz[m] = batch[m];
+    return LBM3D_OK;
+}
+
+// LBM3D_TUNE_CACHE: loaded once per process before the first lookup, saved
+// after every tuning.
+bool g_env_loaded = false;
+const char* env_cache() { return std::getenv("LBM3D_TUNE_CACHE"); }
+void env_load_locked()
+{
+    if (g_env_loaded) return;
+    g_env_loaded = true;
+    if (const char* p = env_cache()) (void)load_locked(p);
+}
+
 }  // namespace
 
 bool cached_tile(int mode, const Grid& g, const FaceBC& bc, TileCfg* out)
 {
     std::lock_guard<std::mutex> lk(g_mu);
+    env_load_locked();
     auto it = g_tiles.find(key_of(mode, g, bc));
     if (it == g_tiles.end()) return false;
     *out = it->second;
@@ -67,6 +157,7 @@ bool cached_tile(int mode, const Grid& g, const FaceBC& bc, TileCfg* out)
 int batch_tile_depth(int mode)
 {
     std::lock_guard<std::mutex> lk(g_mu);
+    env_load_locked();
     return (mode >= 0 && mode < 3) ? g_batch_tz[mode] : 0;
 }
 
@@ -113,17 +204,36 @@ extern "C" int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t*
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_mu);
+        env_load_locked();
         g_tiles[key_of(h->mode, h->g, h->bc)] = best;
+        if (const char* p = env_cache()) (void)save_locked(p);
     }
     if (by) *by = best.by;
     if (tz) *tz = best.tz;
     return LBM3D_OK;
 }
 
+extern "C" int32_t lbm3d_tune_save(const char* path)
+{
+    if (!path || !*path) return LBM3D_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    env_load_locked();
+    return save_locked(path);
+}
+
+extern "C" int32_t lbm3d_tune_load(const char* path)
+{
+    if (!path || !*path) return LBM3D_E_INVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    env_load_locked();
+    return load_locked(path);
+}
+
 extern "C" int32_t lbm3d_batch_set_depth(int32_t precision, int32_t tz)
 {
     if (precision < LBM3D_FP64 || precision > LBM3D_FP32_T64 || tz < 0 || tz > 65535) return LBM3D_E_INVAL;
     std::lock_guard<std::mutex> lk(g_mu);
+    env_load_locked();
     g_batch_tz[precision] = tz;
     return LBM3D_OK;
 }
@@ -171,7 +281,9 @@ extern "C" int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches
     if (e != hipSuccess) return herr2(e);
     {
         std::lock_guard<std::mutex> lk(g_mu);
+        env_load_locked();
         g_batch_tz[hs[0]->mode] = best_tz;
+        if (const char* p = env_cache()) (void)save_locked(p);
     }
     if (tz) *tz = best_tz;
     return LBM3D_OK;

@@ -80,6 +80,8 @@ def _load():
         "lbm3d_step_profiled": (I32, [P, I64, D, D]),
         "lbm3d_set_tile": (I32, [P, I32, I32]),
         "lbm3d_tune": (I32, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "lbm3d_tune_save": (I32, [ctypes.c_char_p]),
+        "lbm3d_tune_load": (I32, [ctypes.c_char_p]),
         "lbm3d_batch_tune": (I32, [ctypes.POINTER(P), I32, I32, ctypes.POINTER(I32)]),
         "lbm3d_batch_set_depth": (I32, [I32, I32]),
         "lbm3d_get_tile": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
@@ -235,6 +237,14 @@ def lbm3d_tune(h, launches: int = 10):
     tz = ctypes.c_int32(0)
     _check(_lib.lbm3d_tune(h, int(launches), ctypes.byref(by), ctypes.byref(tz)), "lbm3d_tune")
     return by.value, tz.value
+
+
+def lbm3d_tune_save(path: str):
+    _check(_lib.lbm3d_tune_save(os.fsencode(path)), "lbm3d_tune_save")
+
+
+def lbm3d_tune_load(path: str):
+    _check(_lib.lbm3d_tune_load(os.fsencode(path)), "lbm3d_tune_load")
 
 
 def lbm3d_sync(h):

@@ -488,3 +488,38 @@ def test_paper_shock_bubble_full_grid(kind):
     err = metrics.rel_l1(mg, mo)
     _report(f"paper_{kind}_298x78x78_fp32t64_3steps", err)
     assert max(err.values()) <= 1e-6
+
+
+def test_tune_cache_on_disk(tmp_path):
+    """The autotuner's result is saved with the device's architecture and,
+    through LBM3D_TUNE_CACHE, a fresh process starts its solves of the same
+    shape with it (two short child processes, one after the other)."""
+    import os
+    import subprocess
+    import sys
+    lbm3d = _lib()
+    case = inputs.shock_bubble(19, grid=(128, 40, 24), precision="fp32_t64", mach=3.0, ratio=2.0)
+    s, _ = gpu_run(case, 2)
+    by, tz = s.tune(3)
+    s.close()
+    path = tmp_path / "tune.txt"
+    lbm3d.lbm3d_tune_save(str(path))
+    lines = path.read_text().splitlines()
+    assert lines[0].startswith("lbm3d-tune 1 gfx")
+    assert f"tile 2 128 40 24 2 1 3 3 3 3 {by} {tz}" in lines
+    # a child process tunes with the cache variable set; the next one reads it
+    env = dict(os.environ, LBM3D_TUNE_CACHE=str(tmp_path / "env.txt"))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    prog = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1010_4135_amd import inputs, lbm3d\n"
+            "c = inputs.shock_bubble(19, grid=(128, 40, 24), precision='fp32_t64', mach=3.0, ratio=2.0)\n"
+            "s = lbm3d.Solver(c.params)\n"
+            "if sys.argv[1] == 'tune':\n"
+            "    s.init(*c.fields); print(*s.tune(3))\n"
+            "else:\n"
+            "    print(*s.get_tile())\n") % root
+    t = subprocess.run([sys.executable, "-c", prog, "tune"], env=env, capture_output=True, text=True, timeout=120)
+    assert t.returncode == 0, t.stderr
+    r = subprocess.run([sys.executable, "-c", prog, "read"], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split() == t.stdout.split()

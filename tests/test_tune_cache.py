@@ -1,0 +1,89 @@
+"""On-disk cache of the autotuner's results (lbm3d_tune_save / load), host
+side: format, round trip, refusal of bad files, and the loaded batch tile
+depth taking effect in the batched step's work plan (no GPU)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1010_4135_amd import inputs
+
+
+def _lib():
+    from paper_1010_4135_amd import lbm3d
+    return lbm3d
+
+
+def _arch():
+    """Architecture the library reports in its header ("none" without a GPU)."""
+    return "none" if _lib().lbm3d_device_count() == 0 else None
+
+
+pytestmark = pytest.mark.skipif(_arch() is None, reason="host-side cache tests run where no GPU is visible")
+
+
+def test_round_trip(tmp_path):
+    lbm3d = _lib()
+    src = tmp_path / "a.txt"
+    src.write_text("lbm3d-tune 1 none\n"
+                   "tile 2 256 128 128 2 1 3 3 3 3 8 32\n"
+                   "tile 0 128 128 128 0 0 0 0 0 0 4 64\n"
+                   "batch 1 64\n")
+    lbm3d.lbm3d_tune_load(str(src))
+    out = tmp_path / "b.txt"
+    lbm3d.lbm3d_tune_save(str(out))
+    lines = out.read_text().splitlines()
+    assert lines[0] == "lbm3d-tune 1 none"
+    for want in ("tile 2 256 128 128 2 1 3 3 3 3 8 32", "tile 0 128 128 128 0 0 0 0 0 0 4 64", "batch 1 64"):
+        assert want in lines
+    assert not os.path.exists(str(out) + ".tmp")
+
+
+def test_loaded_batch_depth_reaches_the_plan(tmp_path):
+    lbm3d = _lib()
+    src = tmp_path / "c.txt"
+    src.write_text("lbm3d-tune 1 none\nbatch 1 16\n")
+    lbm3d.lbm3d_tune_load(str(src))
+    p = inputs.make_params((64, 8, 48), (0,) * 6, precision="fp32")
+    tiles, _, _ = lbm3d.lbm3d_batch_plan([p], tz=0, cus=256)
+    assert set((tiles[:, 6] - tiles[:, 5]).tolist()) == {16}
+    src.write_text("lbm3d-tune 1 none\nbatch 1 48\n")
+    lbm3d.lbm3d_tune_load(str(src))
+    tiles, _, _ = lbm3d.lbm3d_batch_plan([p], tz=0, cus=256)
+    assert set((tiles[:, 6] - tiles[:, 5]).tolist()) == {48}
+    lbm3d.lbm3d_batch_set_depth("fp32", 0)
+
+
+@pytest.mark.parametrize("text", [
+    "",                                              # no header
+    "lbm3d-tune 2 none\n",                           # unknown version
+    "lbm3d-tune 1 gfx950\n",                         # another architecture
+    "lbm3d-tune 1 none\ntile 2 256 128 128 2 1 3 3 3 3 7 32\n",   # no such tile height
+    "lbm3d-tune 1 none\ntile 0 256 128 128 2 1 3 3 3 3 8 32\n",   # 8-row tiles are FP32 only
+    "lbm3d-tune 1 none\ntile 2 256 128 128 2 1 3 3 3 9 8 32\n",   # no such boundary kind
+    "lbm3d-tune 1 none\nbatch 3 16\n",               # no such precision
+    "lbm3d-tune 1 none\nbatch 1 0\n",
+    "lbm3d-tune 1 none\nsomething 1 2\n",
+])
+def test_bad_files_are_refused_and_change_nothing(tmp_path, text):
+    lbm3d = _lib()
+    lbm3d.lbm3d_batch_set_depth("fp32", 24)
+    src = tmp_path / "bad.txt"
+    src.write_text(text + "batch 1 40\n")
+    with pytest.raises(lbm3d.LbmError) as ei:
+        lbm3d.lbm3d_tune_load(str(src))
+    assert ei.value.code == lbm3d.E_INVAL
+    p = inputs.make_params((64, 8, 48), (0,) * 6, precision="fp32")
+    tiles, _, _ = lbm3d.lbm3d_batch_plan([p], tz=0, cus=256)
+    assert set((tiles[:, 6] - tiles[:, 5]).tolist()) == {24}
+    lbm3d.lbm3d_batch_set_depth("fp32", 0)
+
+
+def test_missing_file_and_unwritable_path(tmp_path):
+    lbm3d = _lib()
+    with pytest.raises(lbm3d.LbmError) as ei:
+        lbm3d.lbm3d_tune_load(str(tmp_path / "nope.txt"))
+    assert ei.value.code == lbm3d.E_NOTFOUND
+    with pytest.raises(lbm3d.LbmError) as ei:
+        lbm3d.lbm3d_tune_save(str(tmp_path / "no_such_dir" / "x.txt"))
+    assert ei.value.code == lbm3d.E_INVAL
