@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm3d.so")
-SOURCES = ["lbm3d_device.hip", "lbm3d_api.cpp", "lbm3d_batch.cpp", "lbm3d_server.cpp", "lbm3d_tune.cpp",
-           "lbm3d_probe.hip", "lbm3d_stability.cpp"]
+SOURCES = ["lbm3d_device.hip", "lbm3d_layout.cpp", "lbm3d_api.cpp", "lbm3d_batch.cpp", "lbm3d_server.cpp",
+           "lbm3d_tune.cpp", "lbm3d_probe.hip", "lbm3d_stability.cpp"]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 # gfx950 only; packed FP32 instructions are switched off for all device code

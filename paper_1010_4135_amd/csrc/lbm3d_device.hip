@@ -357,7 +357,6 @@ __global__ void k_moments(Grid g, Model<double> md, Model<float> mf,
 // Per block: FP64 sums over its nodes of (rho, rho u, energy) reduced by a
 // fixed LDS tree; then one block adds the per-block partials in a fixed
 // tree.  No floating atomics, so the totals are bitwise reproducible.
-constexpr int RB = 256;
 
 template <int MODE>
 __global__ void __launch_bounds__(RB)
@@ -468,63 +467,6 @@ hipError_t launch_init(int mode, const Grid& g, const Model<double>& md, const d
     return hipGetLastError();
 }
 
-bool tiled_fits(int mode, const Grid& g)
-{
-    // the tiled kernels address a velocity plane with 32-bit byte offsets
-    const int64_t es = mode == MODE_FP64 ? 8 : 4;
-    return g.sv * es < ((int64_t)1 << 31);
-}
-
-TileCfg default_tile(int mode, const Grid& g)
-{
-    // measured on MI355X at 256x128x128: 64x8x32 tiles (FP32 modes) and
-    // 64x4x64 (FP64); a short z extent leaves too few workgroups on small grids
-    TileCfg t;
-    if (!tiled_fits(mode, g)) {
-        t.by = 0;
-        t.tz = 1;
-        return t;
-    }
-    t.by = mode == MODE_FP64 ? 4 : 8;
-    t.tz = mode == MODE_FP64 ? 64 : 32;
-    if (g.nz < 2 * t.tz) t.tz = std::max(2, g.nz / 4);
-    return t;
-}
-
-bool tile_supported(int mode, const Grid& g, const TileCfg& t)
-{
-    if (t.tz < 1) return false;
-    if (t.by == 0) return true;
-    if (!tiled_fits(mode, g)) return false;
-    if (t.by == 2 || t.by == 4) return true;
-    return t.by == 8 && mode != MODE_FP64;
-}
-
-uint32_t ghost_faces(const Grid& g, const FaceBC& bc, bool tiled)
-{
-    uint32_t m = 0;
-    for (int face = 0; face < 6; face++) {
-        const int kind = bc.kind[face], axis = face >> 1;
-        if (kind == BC_INFLOW) continue;
-        if (tiled && axis == 0 && g.nx % TILE_X == 0) continue;
-        if (tiled && kind == BC_PERIODIC) continue;
-        m |= 1u << face;
-    }
-    return m;
-}
-
-void x_fixed_states(const double (*inflow)[5], double (&xin)[2][5])
-{
-    for (int s = 0; s < 2; s++) {
-        const double* st = inflow[s];
-        xin[s][0] = st[0];
-        xin[s][1] = st[1];
-        xin[s][2] = st[2];
-        xin[s][3] = st[3];
-        xin[s][4] = st[0] > 0.0 ? st[4] / st[0] : 0.0;  // T = p / rho
-    }
-}
-
 template <int MODE, int BY>
 static void launch_tiled(const Grid& g, const FaceBC& bc, int tz, const Model<double>& md,
                          const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
@@ -617,12 +559,6 @@ hipError_t launch_moments(int mode, const Grid& g, const Model<double>& md, cons
     const Model<float> mf = to_float(md);
     LBM3D_DISPATCH(mode, k_moments<MD><<<dim3(blocks_for(n, 256)), dim3(256), 0, s>>>(g, md, mf, (const typename Types<MD>::S*)f, q5));
     return hipGetLastError();
-}
-
-int conserved_blocks(const Grid& g)
-{
-    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-    return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + RB - 1) / RB));
 }
 
 hipError_t launch_conserved(int mode, const Grid& g, const Model<double>& md, const void* f,

@@ -140,8 +140,10 @@ hipError_t launch_gather_health(const BatchSolve* solves, int n, uint32_t* out, 
 hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles,
                              BatchQueue* queue, int nlists, int nblocks, int parity, hipStream_t s);
 
-// block shape of the untiled step kernel; x extent of a tile of the tiled one
+// block shape of the untiled step kernel; x extent of a tile of the tiled one;
+// block size of the conservation reduction
 constexpr int TX = 64, TY = 4;
+constexpr int RB = 256;
 constexpr int TILE_X = 64;
 
 // Rows hold the interior only (mx = nx) when 64-wide tiles cover x exactly:
