@@ -166,10 +166,11 @@ int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz);
 int32_t lbm3d_get_tile(lbm3d_t h, int32_t* by, int32_t* tz);
 
 /* Autotuner of the launch shape.  Times every supported tile shape (and the
- * untiled kernel) over `launches` launches each (<= 0: 10), with HIP events
- * on the solver's stream, by stepping from the current level into the other
- * buffer again and again; the solve's state and step count are unchanged.
- * Keeps the fastest shape (as lbm3d_set_tile) and remembers it for the
+ * untiled kernel) over `launches` launches each (<= 0: 10), in three
+ * interleaved rounds, with HIP events on the solver's stream, by stepping
+ * from the current level into the other buffer again and again; the
+ * solve's state and step count are unchanged.  Keeps the shape with the
+ * fastest round (as lbm3d_set_tile) and remembers it for the
  * process: later lbm3d_create calls for the same precision, grid and
  * boundary kinds start with it.  Blocking.  by / tz (may be NULL) receive
  * the shape.  E_STATE before lbm3d_init. */
@@ -324,8 +325,9 @@ int32_t lbm3d_batch_plan(const lbm3d_params* ps, int32_t count, int32_t tz, int3
 /* Autotuner of the batched step: times the persistent launch over the given
  * solves (same rules as lbm3d_batch_step) for tile depths 16, 32, 64 and 128
  * (a depth at or beyond a solve's nz gives whole columns), over `launches`
- * launches each (<= 0: 5), recomputing the same next level each time
- * (states unchanged), and keeps the fastest depth for every later batched
+ * launches each (<= 0: 5) in three interleaved rounds, recomputing the same
+ * next level each time (states unchanged), and keeps the depth with the
+ * fastest round for every later batched
  * step (lbm3d_batch_step and servers) of that precision in this process.
  * Blocking.  *tz (may be NULL) receives the depth. */
 int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches, int32_t* tz);

@@ -97,8 +97,7 @@ k_step(Grid g, Model<double> md, Model<float> mf, const typename Types<MODE>::S*
 #pragma unroll
     for (int i = 0; i < NV; i++) fc[i] = static_cast<C>(f[i * g.sv + site]);
     const Macro<M> q = moments<M, C>(fc, mm);
-    const uint32_t hb = health_bits(q);
-    if (hb) atomicOr(health, hb);
+    report_health(health, health_bits(q));
     C feq[NV];
     equilibrium<C, M>(q, mm, mc, feq);
     int64_t xo[4];

@@ -166,6 +166,21 @@ __device__ __forceinline__ uint32_t health_bits(const Macro<M>& q)
     return h;
 }
 
+// Add health bits to a solve's health word, one atomic per wavefront: the
+// bits are OR-ed over the wavefront's live lanes first.  A per-lane atomic
+// would put every unhealthy node of a tile on the same address (a solve with
+// T <= 0 along a whole interface plane then queues thousands of atomics on
+// one L2 channel at each tile end).
+__device__ __forceinline__ void report_health(uint32_t* health, uint32_t h)
+{
+    uint32_t w = 0;
+    if (__ballot(h & H_NONFINITE)) w |= H_NONFINITE;
+    if (__ballot(h & H_RHO)) w |= H_RHO;
+    if (__ballot(h & H_T)) w |= H_T;
+    const unsigned first = (unsigned)__ffsll((long long)__ballot(1)) - 1u;
+    if (w && __lane_id() == first) atomicOr(health, w);
+}
+
 // ------------------------------------------------------- per-node update --
 // Explicit fused multiply-add, so that every kernel rounds the update the
 // same way whatever the compiler's contraction choices in its context.

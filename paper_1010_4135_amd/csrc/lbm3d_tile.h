@@ -619,7 +619,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
         plane(std::integral_constant<int, 3>{}, z);
         if (++z >= z1) break;
     }
-    if (act && hacc) atomicOr(A.health, hacc);
+    report_health(A.health, act ? hacc : 0u);
 }
 
 // Does the tile at x0 form extrapolating or reflecting x layers itself?

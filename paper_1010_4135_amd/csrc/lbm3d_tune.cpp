@@ -2,8 +2,9 @@
 // single solve and the tile depth of the batched step.  Each candidate is
 // timed with HIP events on the solve's own data, launching the step from
 // the current buffer into the other one again and again (the current level
-// is never overwritten, so the state of the solves is unchanged), and the
-// fastest shape is kept and remembered for later solves of the same shape.
+// is never overwritten, so the state of the solves is unchanged), in three
+// interleaved rounds; the shape with the fastest round is kept and
+// remembered for later solves of the same shape.
 #include "lbm3d_api_impl.h"
 #include "lbm3d_batch.h"
 
@@ -20,6 +21,8 @@
 
 namespace lbm3d {
 namespace {
+
+constexpr int TUNE_ROUNDS = 3;  // interleaved timing rounds per candidate
 
 struct ShapeKey {
     std::array<int, 10> v;  // precision, nx, ny, nz, six boundary kinds
@@ -180,26 +183,38 @@ extern "C" int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t*
     if (e != hipSuccess) return herr2(e);
     const void* f = h->f[h->cur];
     void* fn = h->f[h->cur ^ 1];  // the next level's buffer: free until the next step
-    TileCfg best = h->tile;
-    float best_ms = -1.0f;
-    for (const TileCfg& t : tile_candidates(h->mode, h->g)) {
-        if (h->upwind2 && t.by != 0) continue;  // the variant runs untiled only
-        auto launch = [&]() {
-            return launch_step(h->mode, h->g, h->bc, t, h->md, h->mf, h->p.inflow, f, fn, h->health, s, h->upwind2);
-        };
-        for (int w = 0; w < 2 && e == hipSuccess; w++) e = launch();
-        if (e == hipSuccess) e = hipEventRecord(h->ev0, s);
-        for (int k = 0; k < launches && e == hipSuccess; k++) e = launch();
-        if (e == hipSuccess) e = hipEventRecord(h->ev1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->ev0, h->ev1);
-        if (e != hipSuccess) return herr2(e);
-        if (best_ms < 0.0f || ms < best_ms) {
-            best_ms = ms;
-            best = t;
+    std::vector<TileCfg> cands;
+    for (const TileCfg& t : tile_candidates(h->mode, h->g))
+        if (!(h->upwind2 && t.by != 0)) cands.push_back(t);  // the variant runs untiled only
+    // every candidate is timed in each of TUNE_ROUNDS interleaved rounds and
+    // keeps its fastest round, so a slow moment of the device does not
+    // decide between two close candidates
+    std::vector<float> ms_best(cands.size(), -1.0f);
+    for (int r = 0; r < TUNE_ROUNDS; r++) {
+        for (size_t c = 0; c < cands.size(); c++) {
+            const TileCfg& t = cands[c];
+            auto launch = [&]() {
+                return launch_step(h->mode, h->g, h->bc, t, h->md, h->mf, h->p.inflow, f, fn, h->health, s,
+                                   h->upwind2);
+            };
+            for (int w = 0; w < (r == 0 ? 2 : 1) && e == hipSuccess; w++) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(h->ev0, s);
+            for (int k = 0; k < launches && e == hipSuccess; k++) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(h->ev1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->ev0, h->ev1);
+            if (e != hipSuccess) return herr2(e);
+            if (ms_best[c] < 0.0f || ms < ms_best[c]) ms_best[c] = ms;
         }
     }
+    TileCfg best = h->tile;
+    float best_ms = -1.0f;
+    for (size_t c = 0; c < cands.size(); c++)
+        if (best_ms < 0.0f || ms_best[c] < best_ms) {
+            best_ms = ms_best[c];
+            best = cands[c];
+        }
     int32_t rc = lbm3d_set_tile(h, best.by, best.tz);
     if (rc) return rc;
     {
@@ -250,32 +265,40 @@ extern "C" int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    int best_tz = 0;
-    float best_ms = -1.0f;
     // chunk depths; a depth at or beyond a member's nz gives whole columns
-    const int tzs[4] = {16, 32, 64, 128};
-    for (int t : tzs) {
-        if (e != hipSuccess) break;
-        BatchPlan plan;
-        rc = plan.build(members, s, t);
+    constexpr int NT = 4;
+    const int tzs[NT] = {16, 32, 64, 128};
+    BatchPlan plans[NT];
+    for (int c = 0; c < NT; c++) {
+        rc = plans[c].build(members, s, tzs[c]);
         if (rc) {
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             return rc;
         }
-        // parity 0 every time: each launch recomputes the same next level
-        for (int w = 0; w < 2 && e == hipSuccess; w++) e = plan.launch_once(s);
-        if (e == hipSuccess) e = hipEventRecord(e0, s);
-        for (int k = 0; k < launches && e == hipSuccess; k++) e = plan.launch_once(s);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
-            best_ms = ms;
-            best_tz = t;
+    }
+    // interleaved rounds, each depth keeping its fastest (as for the tiles)
+    float ms_best[NT] = {-1.0f, -1.0f, -1.0f, -1.0f};
+    for (int r = 0; r < TUNE_ROUNDS && e == hipSuccess; r++) {
+        for (int c = 0; c < NT && e == hipSuccess; c++) {
+            // parity 0 every time: each launch recomputes the same next level
+            for (int w = 0; w < (r == 0 ? 2 : 1) && e == hipSuccess; w++) e = plans[c].launch_once(s);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int k = 0; k < launches && e == hipSuccess; k++) e = plans[c].launch_once(s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && (ms_best[c] < 0.0f || ms < ms_best[c])) ms_best[c] = ms;
         }
     }
+    int best_tz = 0;
+    float best_ms = -1.0f;
+    for (int c = 0; c < NT; c++)
+        if (ms_best[c] >= 0.0f && (best_ms < 0.0f || ms_best[c] < best_ms)) {
+            best_ms = ms_best[c];
+            best_tz = tzs[c];
+        }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return herr2(e);

@@ -212,6 +212,59 @@ def test_nonfinite_state_is_flagged():
     assert ei.value.code == lbm3d.E_NONFINITE
 
 
+def _planted_health_case(precision):
+    """A smooth periodic state with rho <= 0 planted at one node (every f
+    negated) and T <= 0 at another (f of the +x and -x axis velocities moved
+    by +a and -a: rho and E unchanged, u_x raised until u^2 > E/rho), and the
+    health bits the oracle's moments give for that level."""
+    case = inputs.smooth_periodic(11, grid=(64, 16, 12), precision=precision)
+    o = oracle.Oracle(case.params)
+    o.init(*case.fields)
+    f = o.get_f()
+    f[:, 3, 5, 7] *= -1.0
+    f[1, 8, 13, 60] += 5.0
+    f[2, 8, 13, 60] -= 5.0
+    prm = case.params
+    q = [oracle.moments_of(prm["c1"], prm["c2"], prm["eta0"], prm["gamma"], f[:, z, y, x])
+         for (z, y, x) in ((3, 5, 7), (8, 13, 60))]
+    expect = 0
+    for rho, _, _, _, T in q:
+        assert abs(rho) > 0.1 and abs(T) > 0.1  # decisions far from rounding
+        expect |= (2 if rho <= 0 else 0) | (4 if T <= 0 else 0)
+    assert expect & 2 and expect & 4
+    return case, f, expect
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_t64", "fp64"])
+def test_planted_health_bits_on_every_path(precision):
+    """The health word is the OR, over the nodes of the level read, of the
+    rho <= 0 and T <= 0 decisions: the same bits from the untiled kernel,
+    two tile shapes and the batched step (whose healthy member stays 0)."""
+    lbm3d = _lib()
+    case, f, expect = _planted_health_case(precision)
+    f = f.astype(np.float64 if precision == "fp64" else np.float32)  # the storage type
+    shapes = [(0, 1), (4, 8)] + ([(8, 16)] if precision != "fp64" else [])
+    for by, tz in shapes:
+        s = lbm3d.Solver(dict(case.params))
+        s.set_tile(by, tz)
+        s.init(*case.fields)
+        s.set_f(f)
+        s.step(1)
+        h, _ = s.status()
+        print(f"[health] {precision} tile {by}x{tz}: {h} (oracle {expect})", flush=True)
+        assert h == expect, (by, tz)
+        s.close()
+    other = inputs.smooth_periodic(12, grid=(32, 16, 8), precision=precision)
+    a, b = lbm3d.Solver(dict(case.params)), lbm3d.Solver(dict(other.params))
+    a.init(*case.fields)
+    a.set_f(f)
+    b.init(*other.fields)
+    lbm3d.lbm3d_batch_step([a.h, b.h], [1, 1])
+    assert a.status()[0] == expect and b.status()[0] == 0
+    a.close()
+    b.close()
+
+
 def test_uniform_states_stay_uniform_on_gpu():
     st = (2.66667, 1.47902, 0.0, 0.0, 4.5)
     prm = inputs.make_params((37, 11, 9), (2, 1, 3, 3, 3, 3), inflow={0: st}, precision="fp64")
