@@ -246,26 +246,31 @@ struct FixedStates {
 };
 
 // Line j (over the selected faces in order) of one solve's boundary layers.
+// Line counts and indices are 32-bit (32-bit division is a short native
+// sequence, 64-bit division a long emulated one): the host accepts only
+// grids whose velocity plane holds fewer than 2e9 elements, so the lines of
+// all six faces, 2 (nx ny + ny nz + nz nx), stay below 4.01e9 < 2^32.
 template <int MODE>
 __device__ __forceinline__ void layer_job(const StepArgs<MODE>& A, const Model<double>& md, const Model<float>& mf,
-                                          const FixedStates* fx, uint32_t faces, int64_t j)
+                                          const FixedStates* fx, uint32_t faces, uint32_t j)
 {
     using C = typename Types<MODE>::C;
     using M = typename Types<MODE>::M;
     const Grid& g = A.g;
+    const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, nz = (uint32_t)g.nz;
 #pragma unroll
     for (int face = 0; face < 6; face++) {
         if (!((faces >> face) & 1)) continue;
         const int axis = face >> 1;
-        const int64_t cnt = axis == 0 ? (int64_t)g.ny * g.nz : axis == 1 ? (int64_t)g.nx * g.nz : (int64_t)g.nx * g.ny;
+        const uint32_t cnt = axis == 0 ? ny * nz : axis == 1 ? nx * nz : nx * ny;
         if (j >= cnt) {
             j -= cnt;
             continue;
         }
         int cx = 0, cy = 0, cz = 0;
-        if (axis == 0) { cy = (int)(j % g.ny); cz = (int)(j / g.ny); }
-        else if (axis == 1) { cx = (int)(j % g.nx); cz = (int)(j / g.nx); }
-        else { cx = (int)(j % g.nx); cy = (int)(j / g.nx); }
+        if (axis == 0) { cy = (int)(j % ny); cz = (int)(j / ny); }
+        else if (axis == 1) { cx = (int)(j % nx); cz = (int)(j / nx); }
+        else { cx = (int)(j % nx); cy = (int)(j / nx); }
         const uint32_t line = (uint32_t)(g.org + (int64_t)cz * g.sz + (int64_t)cy * g.sy + cx);
         const uint32_t st = axis == 0 ? 1u : axis == 1 ? (uint32_t)g.sy : (uint32_t)g.sz;
         const int n = axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz;
@@ -302,7 +307,7 @@ template <int MODE>
 __global__ void __launch_bounds__(64)
 k_layers(StepArgs<MODE> A, Model<double> md, Model<float> mf, FixedStates fx, uint32_t faces)
 {
-    layer_job<MODE>(A, md, mf, &fx, faces, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    layer_job<MODE>(A, md, mf, &fx, faces, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Boundary layers of many solves in one launch: job k covers workgroups
@@ -324,7 +329,7 @@ k_layers_batch(const BatchSolve* __restrict__ solves, const BatchLayerJob* __res
     A.f = nullptr;
     A.fn = (S*)d.f[cur ^ 1];
     A.health = nullptr;
-    layer_job<MODE>(A, d.md, d.mf, nullptr, jb.faces, (int64_t)(b - jb.first) * 64 + threadIdx.x);
+    layer_job<MODE>(A, d.md, d.mf, nullptr, jb.faces, (uint32_t)(b - jb.first) * 64u + threadIdx.x);
 }
 
 // -------------------------------------------------------------- moments --

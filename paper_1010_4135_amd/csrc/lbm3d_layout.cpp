@@ -44,7 +44,10 @@ uint32_t ghost_faces(const Grid& g, const FaceBC& bc, bool tiled)
     for (int face = 0; face < 6; face++) {
         const int kind = bc.kind[face], axis = face >> 1;
         if (kind == BC_INFLOW) continue;
-        if (tiled && axis == 0 && g.nx % TILE_X == 0) continue;
+        // the tiles form the -x layers, and the +x layers unless the last
+        // tile holds a single column (see x_forms)
+        if (tiled && face == 0) continue;
+        if (tiled && face == 1 && g.nx % TILE_X != 1) continue;
         if (tiled && kind == BC_PERIODIC) continue;
         m |= 1u << face;
     }

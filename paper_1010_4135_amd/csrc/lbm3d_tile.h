@@ -337,17 +337,25 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     const int64_t sv = g.sv, sy = g.sy, sz = g.sz;
     const int zmax = g.nz + 1;
     // Faces handled inside the tile, so their layers need not be in memory:
-    //  - x faces when 64-wide tiles cover x exactly: periodic halo columns
-    //    wrap; fixed-state columns are written into both LDS planes once;
-    //    extrapolated and reflecting columns are formed per plane from the
-    //    moments of the nodes next to the face (Sec. 4 (2)), by the
-    //    wavefront that owns the row;
+    //  - the -x face (first tile): fixed-state halo columns are written into
+    //    both LDS planes once; extrapolated and reflecting columns are
+    //    formed per plane from the moments of the nodes next to the face
+    //    (Sec. 4 (2)), by the wavefront that owns the row;
+    //  - the +x face (last tile): the same, into the halo columns when
+    //    64-wide tiles cover x exactly, else into the row's own LDS columns
+    //    just past the face (those of lanes xr, xr + 1, which are outside
+    //    the grid); with a one-column tail (xr = 1) the layers stay in
+    //    memory, as do fixed-state layers past a ragged edge (the lanes
+    //    there load them from memory with their own column);
     //  - periodic faces: columns, rows and planes wrap (any nx).
     // Other layers are read from memory.  Every load is clamped into the
     // padded array: nodes beyond the last layer are never read by an
     // active node's stencil.
     const bool xin_tile = (g.nx % TILE_X) == 0;
-    const bool lf = xin_tile && x0 == 0, rf = xin_tile && x0 + TILE_X == g.nx;
+    const int xr = g.nx - x0;  // interior columns from x0 to the +x face
+    const bool lf = x0 == 0;
+    const bool rf = xr <= TILE_X && xr >= 2;  // this tile forms the +x layers
+    const bool redge = xin_tile && xr == TILE_X;  // ... in its halo columns
     const int kL = A.bc.kind[0], kR = A.bc.kind[1];
     const bool xwrap = kL == BC_PERIODIC;
     const bool ywrap = A.bc.kind[2] == BC_PERIODIC;
@@ -456,7 +464,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     // into both planes once (lanes 0, 1: columns of layers -1, -2; lanes
     // 2, 3: layers nx, nx+1)
     {
-        const bool lfix = lf && kL == BC_INFLOW, rfix = rf && kR == BC_INFLOW;
+        const bool lfix = lf && kL == BC_INFLOW, rfix = redge && kR == BC_INFLOW;
         if (lfix || rfix) {
             const int side = tx >= 2 ? 1 : 0;
             Macro<M> qf;
@@ -482,20 +490,25 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     // layers of an extrapolating or reflecting x face of one plane from the
     // moments of this row's two nodes next to the face, one value per lane:
     // lane 32 s + 15 j + i (i < 15, j < 2) forms velocity i of layer j+1 of
-    // face s (0: -x, 1: +x) and writes it into the plane's halo column,
-    // which only this wavefront reads (so no barrier orders it)
+    // face s (0: -x, 1: +x) and writes it into the plane's LDS column of
+    // that layer node (a halo column, or past a ragged +x face a column of
+    // the row itself, overwriting what the lane there staged), which only
+    // this wavefront reads (so no barrier orders it)
     auto form_x = [&](const Macro<M>& mq, TilePlane<BY, S>& T) {
         const int side = tx >> 5, ll = tx & 31;
         const int j = ll >= NV ? 1 : 0, iv = min(ll - NV * j, NV - 1);
         const int kind = side ? kR : kL;
         const bool on = ll < 2 * NV && (side ? rf : lf) && (kind == BC_OUTFLOW || kind == BC_REFLECT);
-        const Macro<M> q0 = shfl_macro(mq, side ? TILE_X - 1 : 0);
-        const Macro<M> q1 = shfl_macro(mq, side ? TILE_X - 2 : 1);
+        // (source lanes clamped into the wavefront: a tile that forms only
+        // the -x layers computes unused +x values)
+        const int xs = min(xr, TILE_X);
+        const Macro<M> q0 = shfl_macro(mq, side ? xs - 1 : 0);
+        const Macro<M> q1 = shfl_macro(mq, side ? max(xs - 2, 0) : 1);
         M c, m;
         layer_coefs(kind, j + 1, c, m);
         const Macro<M> qs = layer_state(q0, q1, c, m, 0);
         const C val = static_cast<C>(feq_vel<M>(iv, eq_coef<M, M>(qs, mm), mm));
-        if (on) T.v[iv][ty + 2][side ? TILE_X + 2 + j : 1 - j] = static_cast<S>(val);
+        if (on) T.v[iv][ty + 2][side ? xr + 2 + j : 1 - j] = static_cast<S>(val);
     };
 
     // stage plane z0 in P[0]; the halo of plane z0+1 waits in set 1
@@ -623,12 +636,14 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
 }
 
 // Does the tile at x0 form extrapolating or reflecting x layers itself?
+// (The first tile forms the -x layers, the last the +x layers unless its
+// tail is a single column; ghost_faces() leaves the same faces out.)
 template <int MODE>
 __device__ __forceinline__ bool x_forms(const StepArgs<MODE>& A, int x0)
 {
-    if ((A.g.nx % TILE_X) != 0) return false;
     auto formed = [](int k) { return k == BC_OUTFLOW || k == BC_REFLECT; };
-    return (x0 == 0 && formed(A.bc.kind[0])) || (x0 + TILE_X == A.g.nx && formed(A.bc.kind[1]));
+    const int xr = A.g.nx - x0;
+    return (x0 == 0 && formed(A.bc.kind[0])) || (xr <= TILE_X && xr >= 2 && formed(A.bc.kind[1]));
 }
 
 template <int MODE, int BY, bool VK = true>

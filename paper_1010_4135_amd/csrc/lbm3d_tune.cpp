@@ -183,6 +183,10 @@ extern "C" int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t*
     if (e != hipSuccess) return herr2(e);
     const void* f = h->f[h->cur];
     void* fn = h->f[h->cur ^ 1];  // the next level's buffer: free until the next step
+    // the untiled candidate reads every boundary layer from memory, also
+    // those a tiled step forms itself and leaves stale there
+    e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, true, h->f[h->cur], s);
+    if (e != hipSuccess) return herr2(e);
     std::vector<TileCfg> cands;
     for (const TileCfg& t : tile_candidates(h->mode, h->g))
         if (!(h->upwind2 && t.by != 0)) cands.push_back(t);  // the variant runs untiled only

@@ -89,6 +89,14 @@ def _small_cases():
     c.params = dict(c.params, bc=(3, 1, 0, 0, 0, 0))
     out.append(("reflect_outflow_64x19x13_yz_wrap", c, 40))
     out.append(("periodic_128x9x7_wrap", inputs.smooth_periodic(14, grid=(128, 9, 7), amp=0.3), 40))
+    # ragged x: the last tile forms the +x layers past the face (2-column
+    # tail) or leaves them in memory (1-column tail)
+    c = inputs.smooth_periodic(24, grid=(66, 11, 7), amp=0.3)
+    c.params = dict(c.params, bc=(3, 1, 1, 3, 0, 0))
+    out.append(("ragged_x_layers_66x11x7", c, 40))
+    c = inputs.smooth_periodic(25, grid=(65, 9, 7), amp=0.3)
+    c.params = dict(c.params, bc=(1, 3, 0, 0, 3, 1))
+    out.append(("ragged_x_tail1_65x9x7", c, 40))
     return out
 
 
@@ -298,10 +306,19 @@ def _tile_cases(precision):
     out.append(c)
     # periodic in every axis with ragged x (70 = 64 + 6) and tiny y
     out.append(inputs.smooth_periodic(19, grid=(70, 5, 11), amp=0.3, precision=precision))
+    # ragged x with extrapolating / reflecting x faces: the last tile forms
+    # the +x layers past the face in its own columns (tails of 2 and 63
+    # columns, one tile holding both faces) or leaves them in memory (a
+    # one-column tail)
+    for seed, grid, bc in ((20, (66, 14, 9), (1, 3, 3, 1, 0, 0)), (21, (127, 10, 9), (3, 3, 1, 1, 0, 0)),
+                           (22, (33, 14, 9), (1, 1, 0, 0, 3, 3)), (23, (65, 14, 9), (3, 1, 0, 0, 1, 1))):
+        c = inputs.smooth_periodic(seed, grid=grid, amp=0.3, precision=precision)
+        c.params = dict(c.params, bc=bc)
+        out.append(c)
     return out
 
 
-@pytest.mark.parametrize("which", range(5))
+@pytest.mark.parametrize("which", range(9))
 @pytest.mark.parametrize("precision", ["fp64", "fp32_t64"])
 def test_results_do_not_depend_on_tile_shape(precision, which):
     """Every launch shape (untiled, and 64 x BY x TZ tiles with ragged edges
