@@ -136,13 +136,14 @@ Grid make_grid(const lbm3d_params* p)
     g.my = (int32_t)my;
     g.sy = mx;
     g.sz = mx * my;
-    // one spare line past the array: the sink of the step kernel's stores
-    // from lanes outside the grid (the right layer nodes of the last row of
-    // a padded array reach two elements past sz * mz)
+    // the sink region of the tiled step's stores from lanes outside the
+    // grid, after one spare line (the right layer nodes of the last row of a
+    // padded array reach two elements past sz * mz)
     g.sink = g.sz * mz + line;
-    // dense rows: the x layers of every row (4 nodes) after the sink line
-    g.xg = dense ? g.sz * mz + 2 * line : 0;
-    const int64_t end = dense ? g.xg + 4 * my * mz : g.sz * mz + 2 * line;
+    const int64_t sink_end = g.sink + (int64_t)SINK_ROWS * TILE_X;
+    // dense rows: the x layers of every row (4 nodes) after the sink region
+    g.xg = dense ? sink_end + line : 0;
+    const int64_t end = dense ? g.xg + 4 * my * mz : sink_end + line;
     // velocity planes are separated by an odd number of 256-byte blocks so
     // that the 15 streams do not start on the same memory channel
     const int64_t blk = 256 / (int64_t)elem_size(p->precision);

@@ -42,7 +42,7 @@ struct Grid {
     int32_t my;          // rows per plane (ny + 4)
     int64_t sy, sz, sv;  // strides of y, z and velocity (elements)
     int64_t org;         // offset of interior node (0,0,0)
-    int64_t sink;        // offset (within a velocity plane) of an element that is never read
+    int64_t sink;        // offset (within a velocity plane) of a region of SINK_ROWS x TILE_X elements that is never read
     int64_t xg;          // offset (within a velocity plane) of the x-layer block, 0 if none
 };
 
@@ -145,12 +145,17 @@ hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const B
 constexpr int TX = 64, TY = 4;
 constexpr int RB = 256;
 constexpr int TILE_X = 64;
+// Lanes of the tiled step outside the grid store unconditionally into a sink
+// region past the array, each to its own element (row y mod SINK_ROWS, its
+// lane): stores that all went to one element would queue on one address,
+// which on ragged grids (every row's last tile overhangs the face) made the
+// tiled step several times slower.
+constexpr int SINK_ROWS = 64;
 
 // Rows hold the interior only (mx = nx) when 64-wide tiles cover x exactly:
 // the tiles then form the x boundary layers themselves and never read them
-// from memory, and the x layers live in a block of their own.  Streaming
-// dense rows reaches about 8 TB/s on a 256-wide grid against about 6 TB/s
-// with rows padded by a cache line holding the layers.
+// from memory, and the x layers live in a block of their own.  Other rows
+// are padded by a cache line that holds the x layers.
 __host__ __device__ inline bool dense_rows(int nx) { return nx % TILE_X == 0; }
 
 }  // namespace lbm3d

@@ -375,9 +375,11 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
     auto wbase = [&](S* p, int i, int zz) { return p + ((int64_t)i * sv + g.org + (int64_t)zz * sz); };
     const uint32_t colb = (uint32_t)((int64_t)yl * sy + xl) * ES;  // this thread's node within a plane
     const uint32_t xlb = (uint32_t)xl * ES;
-    // lanes outside the grid store to a sink element past the end of each
-    // velocity plane that is never read, so every store is unconditional
-    const int64_t sinkrel = g.sink - g.org;
+    // lanes outside the grid store into the sink region past the end of each
+    // velocity plane, which is never read, so every store is unconditional;
+    // each lane has its own element there (row y mod SINK_ROWS, which is
+    // uniform per wavefront, and its lane)
+    const int64_t sinkrel = g.sink - g.org + (int64_t)((y0 + wave) & (SINK_ROWS - 1)) * TILE_X;
 
     // ---- z ring and carried minmods
     C q[NV][4];
@@ -557,7 +559,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
         if constexpr (XF) form_x(mac, cur);
         C feq[NV];
         equilibrium<C, M>(mac, mm, mc, feq);
-        const uint32_t outb = act ? colb : (uint32_t)((sinkrel - (int64_t)z * sz) * ES);
+        const uint32_t outb = act ? colb : (uint32_t)((sinkrel - (int64_t)z * sz) * ES) + (uint32_t)tx * ES;
         S* po = wbase(fn, 0, z);
         static_for<NV>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
