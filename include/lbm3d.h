@@ -166,10 +166,13 @@ int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz);
 int32_t lbm3d_get_tile(lbm3d_t h, int32_t* by, int32_t* tz);
 
 /* Autotuner of the launch shape.  Times every supported tile shape (and the
- * untiled kernel) over `launches` launches each (<= 0: 10), in three
- * interleaved rounds, with HIP events on the solver's stream, by stepping
- * from the current level into the other buffer again and again; the
- * solve's state and step count are unchanged.  Keeps the shape with the
+ * untiled kernel) over `launches` steps each (<= 0: 10), in three
+ * interleaved rounds, with HIP events on the solver's stream.  The trials
+ * are real steps (alternating buffers, boundary layers included); the
+ * current level and the health word are copied to temporary device memory
+ * (one distribution buffer) first and restored afterwards, so the solve's
+ * state and step count are unchanged (without memory for the copy, each
+ * trial recomputes the current level instead).  Keeps the shape with the
  * fastest round (as lbm3d_set_tile) and remembers it for the
  * process: later lbm3d_create calls for the same precision, grid and
  * boundary kinds start with it.  Blocking.  by / tz (may be NULL) receive
@@ -325,9 +328,11 @@ int32_t lbm3d_batch_plan(const lbm3d_params* ps, int32_t count, int32_t tz, int3
 /* Autotuner of the batched step: times the persistent launch over the given
  * solves (same rules as lbm3d_batch_step) for tile depths 16, 32, 64 and 128
  * (a depth at or beyond a solve's nz gives whole columns), over `launches`
- * launches each (<= 0: 5) in three interleaved rounds, recomputing the same
- * next level each time (states unchanged), and keeps the depth with the
- * fastest round for every later batched
+ * steps each (<= 0: 5) in three interleaved rounds, as real steps over
+ * alternating buffers with the solves' current levels and health words
+ * saved to temporary device memory and restored afterwards (states
+ * unchanged; without memory for the copies each trial recomputes the
+ * current levels), and keeps the depth with the fastest round for every later batched
  * step (lbm3d_batch_step and servers) of that precision in this process.
  * Blocking.  *tz (may be NULL) receives the depth. */
 int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches, int32_t* tz);

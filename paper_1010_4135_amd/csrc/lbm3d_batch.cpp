@@ -301,10 +301,10 @@ int32_t BatchPlan::health(std::vector<uint32_t>& out, hipStream_t s)
     return herr(e);
 }
 
-hipError_t BatchPlan::launch_once(hipStream_t s)
+hipError_t BatchPlan::launch_at(int parity, hipStream_t s)
 {
     last_stream_ = s;
-    return enqueue(0, s);
+    return enqueue(parity & 1, s);
 }
 
 hipError_t BatchPlan::enqueue(int parity, hipStream_t s)

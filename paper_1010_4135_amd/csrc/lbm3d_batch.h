@@ -45,10 +45,10 @@ public:
     // Device bytes the tables of `members` need at tile depth tz (0: the
     // tuned or default depth).
     static size_t table_bytes(const std::vector<lbm3d_solver*>& members, int tz = 0);
-    // One step of every member from the build-time buffers into the other
-    // ones, without advancing anything (for timing: repeated launches
-    // recompute the same next level).
-    hipError_t launch_once(hipStream_t s);
+    // One step of every member from its buffer of the given parity
+    // (relative to build) into the other one, boundary layers included,
+    // without advancing the members' step counters or parity (for timing).
+    hipError_t launch_at(int parity, hipStream_t s);
     // Enqueue k steps of every member on `s` and update the members'
     // buffer parity and step counters; `graphs` = false launches every step
     // directly (no graph is instantiated).

@@ -181,37 +181,66 @@ extern "C" int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t*
     hipStream_t s = h->stream;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return herr2(e);
-    const void* f = h->f[h->cur];
-    void* fn = h->f[h->cur ^ 1];  // the next level's buffer: free until the next step
-    // the untiled candidate reads every boundary layer from memory, also
-    // those a tiled step forms itself and leaves stale there
-    e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, true, h->f[h->cur], s);
-    if (e != hipSuccess) return herr2(e);
     std::vector<TileCfg> cands;
     for (const TileCfg& t : tile_candidates(h->mode, h->g))
         if (!(h->upwind2 && t.by != 0)) cands.push_back(t);  // the variant runs untiled only
+    // Trials are real steps: they alternate the two buffers and write the
+    // candidate's boundary layers, as stepping does, so that each step reads
+    // what the one before wrote (from HBM: the step's stores stream past the
+    // caches).  Recomputing one level again and again would read it from the
+    // memory-side cache and rate some shapes far too fast (64 x 4 x 32 at
+    // 127 us against 200 us when stepping, on the 256x128x128 workload).  The
+    // current level (its whole buffer) and the health word are saved first
+    // and restored afterwards, so the solve's state is unchanged.  Without
+    // device memory for the copy the trials recompute the current level.
+    const size_t fb = f_bytes(h->g, h->mode);
+    void* backup = nullptr;
+    if (hipMalloc(&backup, fb) != hipSuccess) {
+        (void)hipGetLastError();
+        backup = nullptr;
+    }
+    uint32_t health0 = 0;
+    if (backup) e = hipMemcpyAsync(backup, h->f[h->cur], fb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&health0, h->health, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int c = h->cur;  // buffer holding the trials' current level
+    auto trial_step = [&](const TileCfg& t) {
+        hipError_t r = launch_step(h->mode, h->g, h->bc, t, h->md, h->mf, h->p.inflow, h->f[c], h->f[c ^ 1],
+                                   h->health, s, h->upwind2);
+        if (!backup) return r;
+        const uint32_t rest = ghost_faces(h->g, h->bc, t.by != 0);
+        if (r == hipSuccess && rest)
+            r = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[c ^ 1], s, rest);
+        c ^= 1;
+        return r;
+    };
     // every candidate is timed in each of TUNE_ROUNDS interleaved rounds and
     // keeps its fastest round, so a slow moment of the device does not
     // decide between two close candidates
     std::vector<float> ms_best(cands.size(), -1.0f);
-    for (int r = 0; r < TUNE_ROUNDS; r++) {
-        for (size_t c = 0; c < cands.size(); c++) {
-            const TileCfg& t = cands[c];
-            auto launch = [&]() {
-                return launch_step(h->mode, h->g, h->bc, t, h->md, h->mf, h->p.inflow, f, fn, h->health, s,
-                                   h->upwind2);
-            };
-            for (int w = 0; w < (r == 0 ? 2 : 1) && e == hipSuccess; w++) e = launch();
+    for (int r = 0; r < TUNE_ROUNDS && e == hipSuccess; r++) {
+        for (size_t k = 0; k < cands.size() && e == hipSuccess; k++) {
+            // every layer of the trials' level in memory: the previous
+            // candidate may have formed some in its tiles only
+            e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, true, h->f[c], s);
+            for (int w = 0; w < (r == 0 ? 2 : 1) && e == hipSuccess; w++) e = trial_step(cands[k]);
             if (e == hipSuccess) e = hipEventRecord(h->ev0, s);
-            for (int k = 0; k < launches && e == hipSuccess; k++) e = launch();
+            for (int n = 0; n < launches && e == hipSuccess; n++) e = trial_step(cands[k]);
             if (e == hipSuccess) e = hipEventRecord(h->ev1, s);
             if (e == hipSuccess) e = hipEventSynchronize(h->ev1);
             float ms = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->ev0, h->ev1);
-            if (e != hipSuccess) return herr2(e);
-            if (ms_best[c] < 0.0f || ms < ms_best[c]) ms_best[c] = ms;
+            if (e == hipSuccess && (ms_best[k] < 0.0f || ms < ms_best[k])) ms_best[k] = ms;
         }
     }
+    // restore the current level and the health word (also after an error)
+    hipError_t e2 = hipSuccess;
+    if (backup) e2 = hipMemcpyAsync(h->f[h->cur], backup, fb, hipMemcpyDeviceToDevice, s);
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(h->health, &health0, sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    if (backup) (void)hipFree(backup);
+    if (e != hipSuccess) return herr2(e);
+    if (e2 != hipSuccess) return herr2(e2);
     TileCfg best = h->tile;
     float best_ms = -1.0f;
     for (size_t c = 0; c < cands.size(); c++)
@@ -281,14 +310,38 @@ extern "C" int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches
             return rc;
         }
     }
+    // Trials are real steps over alternating buffers (see lbm3d_tune): the
+    // members' current buffers and health words are saved first and
+    // restored afterwards.  Without device memory for the copies the trials
+    // recompute the current level.
+    std::vector<size_t> off(count + 1, 0);
+    for (int32_t k = 0; k < count; k++) off[k + 1] = off[k] + f_bytes(hs[k]->g, hs[k]->mode);
+    char* backup = nullptr;
+    if (e == hipSuccess && hipMalloc((void**)&backup, off[count]) != hipSuccess) {
+        (void)hipGetLastError();
+        backup = nullptr;
+    }
+    std::vector<uint32_t> health0(count, 0u);
+    for (int32_t k = 0; k < count && e == hipSuccess; k++) {
+        if (backup)
+            e = hipMemcpyAsync(backup + off[k], hs[k]->f[hs[k]->cur], off[k + 1] - off[k], hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&health0[k], hs[k]->health, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     // interleaved rounds, each depth keeping its fastest (as for the tiles)
     float ms_best[NT] = {-1.0f, -1.0f, -1.0f, -1.0f};
+    int parity = 0;  // buffers holding the trials' current level (the same for every plan)
+    auto trial = [&](BatchPlan& p) {
+        hipError_t r = p.launch_at(parity, s);
+        if (backup) parity ^= 1;
+        return r;
+    };
     for (int r = 0; r < TUNE_ROUNDS && e == hipSuccess; r++) {
         for (int c = 0; c < NT && e == hipSuccess; c++) {
-            // parity 0 every time: each launch recomputes the same next level
-            for (int w = 0; w < (r == 0 ? 2 : 1) && e == hipSuccess; w++) e = plans[c].launch_once(s);
+            for (int w = 0; w < (r == 0 ? 2 : 1) && e == hipSuccess; w++) e = trial(plans[c]);
             if (e == hipSuccess) e = hipEventRecord(e0, s);
-            for (int k = 0; k < launches && e == hipSuccess; k++) e = plans[c].launch_once(s);
+            for (int k = 0; k < launches && e == hipSuccess; k++) e = trial(plans[c]);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.0f;
@@ -296,6 +349,17 @@ extern "C" int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches
             if (e == hipSuccess && (ms_best[c] < 0.0f || ms < ms_best[c])) ms_best[c] = ms;
         }
     }
+    // restore the members' current levels and health words (also after an error)
+    hipError_t e2 = hipSuccess;
+    for (int32_t k = 0; k < count && e2 == hipSuccess; k++) {
+        if (backup)
+            e2 = hipMemcpyAsync(hs[k]->f[hs[k]->cur], backup + off[k], off[k + 1] - off[k], hipMemcpyDeviceToDevice, s);
+        if (e2 == hipSuccess)
+            e2 = hipMemcpyAsync(hs[k]->health, &health0[k], sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    }
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    if (backup) (void)hipFree(backup);
+    if (e == hipSuccess) e = e2;
     int best_tz = 0;
     float best_ms = -1.0f;
     for (int c = 0; c < NT; c++)

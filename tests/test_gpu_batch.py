@@ -177,10 +177,11 @@ def test_batch_autotuner_keeps_states():
         s.step(3)
         solvers.append(s)
     before = [s.get_f() for s in solvers]
+    health = [s.status()[0] for s in solvers]
     tz = lbm3d.lbm3d_batch_tune([s.h for s in solvers], 3)
     assert tz in (16, 32, 64, 128)
-    for s, f in zip(solvers, before):
-        assert np.array_equal(s.get_f(), f) and s.status()[1] == 3
+    for s, f, h in zip(solvers, before, health):
+        assert np.array_equal(s.get_f(), f) and s.status() == (h, 3)
     lbm3d.lbm3d_batch_step([s.h for s in solvers], [9] * len(solvers))
     for c, s in zip(cases, solvers):
         assert np.array_equal(s.get_f(), _alone(c, 12)), c.name
