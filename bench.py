@@ -43,7 +43,7 @@ Beside it:
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S]
                   [--no-batch] [--no-serve] [--no-cpu-baseline] [--copy-check]
-                  [--batch-only] [--serve-requests N]
+                  [--batch-only] [--serve-requests N] [--stores auto|non-temporal|plain]
 """
 from __future__ import annotations
 
@@ -79,9 +79,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision: str):
+def measured_traffic(precision: str, stores: str):
     """Counter-measured HBM bytes per step-kernel launch from the committed
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source with the same
+    precision and store kind."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -89,7 +90,8 @@ def measured_traffic(precision: str):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_source_hash() or kv.get("precision") != precision:
+    if (kv.get("kernel_source_hash") != kernel_source_hash() or kv.get("precision") != precision
+            or kv.get("stores") != stores):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -370,6 +372,9 @@ def main():
     ap.add_argument("--copy-check", action="store_true",
                     help="also run the checkpoint pack (a plain copy of 15 x nodes elements) for counter calibration")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--stores", choices=["auto", "non-temporal", "plain"], default="auto",
+                    help="store kind of the headline's tiled step: the autotuner's choice (default), or "
+                         "pinned after tuning (for profiles taken with a known kind)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched step of the 64-solve mix (--steps steps) and print its rate")
     args = ap.parse_args()
@@ -409,6 +414,8 @@ def main():
     t_tune = time.perf_counter()
     s.tune(10)
     t_tune = time.perf_counter() - t_tune
+    if args.stores != "auto":
+        s.set_streaming(args.stores == "non-temporal")
     s.step(args.warmup)
     # runs of 32 steps replay a captured graph: capture it here, outside the
     # timed region (the state advances 32 more steps, untimed)
@@ -430,6 +437,7 @@ def main():
         for _ in range(3):
             s.get_f()
     by, tz = s.get_tile()
+    stores = "non-temporal" if s.streaming() else "plain"
     bps = BYTES_PER_SITE[args.precision]
     achieved = case.sites * bps / (kernel_ms / 1e3) / 1e9
     out = {
@@ -452,12 +460,13 @@ def main():
             "grid": [nx, ny, nz], "precision": args.precision, "seed": args.seed,
             "mach": round(case.meta["mach"], 4), "density_ratio": round(case.meta["ratio"], 4),
             "tile": [64, by, tz], "tile_from": "autotuner", "tune_s": round(t_tune, 3),
+            "stores": stores,
             "graph_capture_steps": graph_prep,
             "wall_s_timed_region": round(wall, 4), "health": health, "steps_done": done,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.precision),
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.precision, stores),
             "kernel": "k_step_tiled", "kernel_ms": round(kernel_ms, 5), "bytes_per_site": bps,
             "sites_per_launch": case.sites,
         },

@@ -161,12 +161,23 @@ int32_t lbm3d_step_profiled(lbm3d_t h, int64_t nsteps, double* total_ms, double*
 /* Launch shape of the fused step kernel: a tile is 64 x `by` nodes in x-y
  * and `tz` nodes deep in z (by = 2, 4 or 8 -- 8 in the FP32 modes only --
  * or 0 for the untiled one-node-per-thread kernel; tz >= 1).  Results are
- * bitwise independent of the shape.  E_INVAL for an unsupported shape. */
+ * bitwise independent of the shape.  E_INVAL for an unsupported shape.
+ * The store kind (below) is kept. */
 int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz);
 int32_t lbm3d_get_tile(lbm3d_t h, int32_t* by, int32_t* tz);
 
-/* Autotuner of the launch shape.  Times every supported tile shape (and the
- * untiled kernel) over `launches` steps each (<= 0: 10), in three
+/* Store kind of the tiled kernels' new level: 1 = non-temporal (streaming
+ * past the caches), 0 = plain.  A solve starts with plain stores when its
+ * two distribution levels fit in 320 MB (the next step then reads much of
+ * its input from the 256 MB memory-side cache), else with non-temporal
+ * ones; the autotuner picks it with the shape.  Results are bitwise
+ * independent of it; the untiled kernel always stores plainly and the
+ * batched step non-temporally.  E_INVAL for a value other than 0 or 1. */
+int32_t lbm3d_set_streaming(lbm3d_t h, int32_t streaming);
+int32_t lbm3d_get_streaming(lbm3d_t h, int32_t* streaming);
+
+/* Autotuner of the launch shape.  Times every supported tile shape with
+ * both store kinds (and the untiled kernel) over `launches` steps each (<= 0: 10), in three
  * interleaved rounds, with HIP events on the solver's stream.  The trials
  * are real steps (alternating buffers, boundary layers included); the
  * current level and the health word are copied to temporary device memory
@@ -179,13 +190,14 @@ int32_t lbm3d_get_tile(lbm3d_t h, int32_t* by, int32_t* tz);
  * the shape.  E_STATE before lbm3d_init. */
 int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t* tz);
 
-/* On-disk cache of the autotuner's results (the tile shape per precision,
- * grid and boundary kinds, and the batch tile depth per precision), so that
- * a later process starts with the tuned shapes without tuning again.  The
- * file is text: a header "lbm3d-tune 1 <arch>" naming the GPU architecture
- * (gcnArchName, "none" without a device) the shapes were timed on, then
- * lines "tile <precision> <nx> <ny> <nz> <six boundary kinds> <by> <tz>" and
- * "batch <precision> <tz>".
+/* On-disk cache of the autotuner's results (the tile shape and store kind
+ * per precision, grid and boundary kinds, and the batch tile depth per
+ * precision), so that a later process starts with the tuned shapes without
+ * tuning again.  The file is text: a header "lbm3d-tune 2 <arch>" naming the
+ * GPU architecture (gcnArchName, "none" without a device) the shapes were
+ * timed on, then lines
+ * "tile <precision> <nx> <ny> <nz> <six boundary kinds> <by> <tz> <streaming>"
+ * and "batch <precision> <tz>".
  * lbm3d_tune_save writes every result of this process (atomically: a
  * temporary file renamed over `path`); E_INVAL if it cannot be written.
  * lbm3d_tune_load merges a file's results into this process's: E_NOTFOUND

@@ -447,13 +447,10 @@ int32_t lbm3d_step_profiled(lbm3d_t h, int64_t nsteps, double* total_ms, double*
     return LBM3D_OK;
 }
 
-int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz)
+// A new launch shape (or store kind) for the solve's next steps.
+static int32_t set_launch(lbm3d_t h, const TileCfg& t)
 {
-    if (!h) return LBM3D_E_INVAL;
-    TileCfg t;
-    t.by = by;
-    t.tz = tz;
-    if (!tile_supported(h->mode, h->g, t) || (h->upwind2 && by != 0)) return LBM3D_E_INVAL;
+    if (!tile_supported(h->mode, h->g, t) || (h->upwind2 && t.by != 0)) return LBM3D_E_INVAL;
     HIPCHK(hipStreamSynchronize(h->stream));
     for (int k = 0; k < 2; k++)
         if (h->graph_exec[k]) {
@@ -467,6 +464,30 @@ int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz)
         HIPCHK(launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, true, h->f[h->cur], h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
     }
+    return LBM3D_OK;
+}
+
+int32_t lbm3d_set_tile(lbm3d_t h, int32_t by, int32_t tz)
+{
+    if (!h) return LBM3D_E_INVAL;
+    TileCfg t = h->tile;  // (the store kind is kept)
+    t.by = by;
+    t.tz = tz;
+    return set_launch(h, t);
+}
+
+int32_t lbm3d_set_streaming(lbm3d_t h, int32_t streaming)
+{
+    if (!h || (streaming != 0 && streaming != 1)) return LBM3D_E_INVAL;
+    TileCfg t = h->tile;
+    t.stream = streaming == 1;
+    return set_launch(h, t);
+}
+
+int32_t lbm3d_get_streaming(lbm3d_t h, int32_t* streaming)
+{
+    if (!h || !streaming) return LBM3D_E_INVAL;
+    *streaming = h->tile.stream ? 1 : 0;
     return LBM3D_OK;
 }
 

@@ -107,7 +107,7 @@ k_step(Grid g, Model<double> md, Model<float> mf, const typename Types<MODE>::S*
 
 // Tiled fused step: one workgroup per 64 x BY x TZ tile (see lbm3d_tile.h).
 
-template <int MODE, int BY>
+template <int MODE, int BY, bool NT>
 __global__ void __launch_bounds__(TILE_X * BY)
 k_step_tiled(StepArgs<MODE> A, Model<double> md, Model<float> mf, int ntx, int nty, int tz)
 {
@@ -120,7 +120,7 @@ k_step_tiled(StepArgs<MODE> A, Model<double> md, Model<float> mf, int ntx, int n
     const int tzi = r / nty;
     const int z0 = tzi * tz;
     const int z1 = min(z0 + tz, A.g.nz);
-    step_tile<MODE, BY>(A, md, mf, txi * TILE_X, tyi * BY, z0, z1, P);
+    step_tile<MODE, BY, true, NT>(A, md, mf, txi * TILE_X, tyi * BY, z0, z1, P);
 }
 
 // Batched fused step: persistent workgroups walk a packed list of tiles from
@@ -190,7 +190,8 @@ k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict_
         keep(A.g.sy); keep(A.g.sz); keep(A.g.sv); keep(A.g.org); keep(A.g.sink); keep(A.g.xg);
         keep(A.f); keep(A.fn);
         keep_model(mf);
-        step_tile<MODE, BY, true>(A, md, mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
+        // (streaming stores: a batch's levels are far larger than the caches)
+        step_tile<MODE, BY, true, true>(A, md, mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
         lds_barrier();  // the plane buffers (and s_k) are reused by the next tile
     }
 }
@@ -472,7 +473,7 @@ hipError_t launch_init(int mode, const Grid& g, const Model<double>& md, const d
 }
 
 template <int MODE, int BY>
-static void launch_tiled(const Grid& g, const FaceBC& bc, int tz, const Model<double>& md,
+static void launch_tiled(const Grid& g, const FaceBC& bc, int tz, bool stream, const Model<double>& md,
                          const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
                          uint32_t* health, hipStream_t s)
 {
@@ -488,7 +489,10 @@ static void launch_tiled(const Grid& g, const FaceBC& bc, int tz, const Model<do
     A.fn = (S*)fn;
     A.health = health;
     x_fixed_states(inflow, A.xin);
-    k_step_tiled<MODE, BY><<<dim3(nb), dim3(TILE_X * BY), 0, s>>>(A, md, mf, ntx, nty, tz);
+    if (stream)
+        k_step_tiled<MODE, BY, true><<<dim3(nb), dim3(TILE_X * BY), 0, s>>>(A, md, mf, ntx, nty, tz);
+    else
+        k_step_tiled<MODE, BY, false><<<dim3(nb), dim3(TILE_X * BY), 0, s>>>(A, md, mf, ntx, nty, tz);
 }
 
 hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg& tc, const Model<double>& md,
@@ -498,13 +502,13 @@ hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg&
     if (upwind2 && tc.by != 0) return hipErrorInvalidValue;
     if (tc.by != 0) {
         switch (tc.by) {
-        case 2: LBM3D_DISPATCH(mode, launch_tiled<MD, 2>(g, bc, tc.tz, md, mf, inflow, f, fn, health, s)); break;
+        case 2: LBM3D_DISPATCH(mode, launch_tiled<MD, 2>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s)); break;
         case 8:
             if (mode == MODE_FP64) return hipErrorInvalidValue;
-            if (mode == MODE_FP32) launch_tiled<MODE_FP32, 8>(g, bc, tc.tz, md, mf, inflow, f, fn, health, s);
-            else launch_tiled<MODE_FP32_T64, 8>(g, bc, tc.tz, md, mf, inflow, f, fn, health, s);
+            if (mode == MODE_FP32) launch_tiled<MODE_FP32, 8>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s);
+            else launch_tiled<MODE_FP32_T64, 8>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s);
             break;
-        default: LBM3D_DISPATCH(mode, launch_tiled<MD, 4>(g, bc, tc.tz, md, mf, inflow, f, fn, health, s)); break;
+        default: LBM3D_DISPATCH(mode, launch_tiled<MD, 4>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s)); break;
         }
         return hipGetLastError();
     }

@@ -100,7 +100,15 @@ hipError_t launch_init(int mode, const Grid& g, const Model<double>& md, const d
 struct TileCfg {
     int by = 4;
     int tz = 16;
+    bool stream = true;  // non-temporal stores of the new level (tiled kernels)
 };
+// Stores of the new level: non-temporal (streaming past the caches) when the
+// two levels of a solve exceed this many bytes, else plain.  A pair of
+// levels that fits the 256 MB memory-side cache is read back from it by the
+// next step when stored plainly (the step on the 298x78x78 grid, 240 MB,
+// takes 61 us against 85 us streaming); larger ones gain nothing there and
+// streaming keeps the L2 for the halo planes.  The autotuner tries both.
+constexpr int64_t STREAM_MIN_BYTES = (int64_t)320 << 20;
 TileCfg default_tile(int mode, const Grid& g);
 bool tile_supported(int mode, const Grid& g, const TileCfg& t);
 // the tiled kernels (single and batched) take this solve

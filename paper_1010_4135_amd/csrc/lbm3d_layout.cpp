@@ -25,6 +25,8 @@ TileCfg default_tile(int mode, const Grid& g)
     }
     t.by = mode == MODE_FP64 ? 4 : 8;
     t.tz = mode == MODE_FP64 ? 64 : 32;
+    const int64_t es = mode == MODE_FP64 ? 8 : 4;
+    t.stream = 2 * NV * g.sv * es > STREAM_MIN_BYTES;
     if (g.nz < 2 * t.tz) t.tz = std::max(2, g.nz / 4);
     return t;
 }

@@ -254,16 +254,21 @@ __device__ __forceinline__ S ld_at(const S* base, uint32_t off)
     asm("" : "+v"(off));
     return *reinterpret_cast<GP>(reinterpret_cast<uint64_t>(base) + (uint64_t)off);
 }
-// Stores of the new level are streaming (non-temporal): they are not read
+// Stores of the new level.  NT: streaming (non-temporal): they are not read
 // again in this step, and keeping them out of the L2 leaves it to the
-// planes that neighbouring tiles read as their halos.
-template <typename S>
+// planes that neighbouring tiles read as their halos.  Otherwise plain,
+// for solves whose two levels fit the memory-side cache, from which the
+// next step then reads them (see STREAM_MIN_BYTES).
+template <bool NT, typename S>
 __device__ __forceinline__ void st_at(S* base, uint32_t off, S v)
 {
     using GP = __attribute__((address_space(1))) S*;
     asm("" : "+v"(off));
     GP p = reinterpret_cast<GP>(reinterpret_cast<uint64_t>(base) + (uint64_t)off);
-    __builtin_nontemporal_store(v, p);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 
 // Index v in [-2, n + 9] wrapped into [0, n) (periodic faces).
@@ -299,8 +304,9 @@ __device__ __forceinline__ Macro<M> shfl_macro(const Macro<M>& q, int l)
 
 // XF: this tile forms extrapolating or reflecting x layers itself (see
 // x_forms(); the caller selects the instantiation per tile).  VK: the FP64
-// model constants may be held in vector registers (see below).
-template <int MODE, int BY, bool XF, bool VK>
+// model constants may be held in vector registers (see below).  NT: the new
+// level is stored non-temporally (see st_at).
+template <int MODE, int BY, bool XF, bool VK, bool NT>
 __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model<double>& md,
                                             const Model<float>& mf, int x0, int y0, int z0, int z1,
                                             TilePlane<BY, typename Types<MODE>::S> (&P)[2])
@@ -611,7 +617,7 @@ __device__ __forceinline__ void step_tile_x(const StepArgs<MODE>& A, const Model
             }
             const C out = node_update<I, C>(f0, feq[I], Dx, Dy, Dz, lx, ly, lz, mc);
             po = sreg(po);
-            st_at(po, outb, static_cast<S>(out));
+            st_at<NT>(po, outb, static_cast<S>(out));
             po += sv;
             ring_load(ic);
         });
@@ -648,15 +654,15 @@ __device__ __forceinline__ bool x_forms(const StepArgs<MODE>& A, int x0)
     return (x0 == 0 && formed(A.bc.kind[0])) || (xr <= TILE_X && xr >= 2 && formed(A.bc.kind[1]));
 }
 
-template <int MODE, int BY, bool VK = true>
+template <int MODE, int BY, bool VK, bool NT>
 __device__ __forceinline__ void step_tile(const StepArgs<MODE>& A, const Model<double>& md,
                                           const Model<float>& mf, int x0, int y0, int z0, int z1,
                                           TilePlane<BY, typename Types<MODE>::S> (&P)[2])
 {
     if (x_forms(A, x0))
-        step_tile_x<MODE, BY, true, VK>(A, md, mf, x0, y0, z0, z1, P);
+        step_tile_x<MODE, BY, true, VK, NT>(A, md, mf, x0, y0, z0, z1, P);
     else
-        step_tile_x<MODE, BY, false, VK>(A, md, mf, x0, y0, z0, z1, P);
+        step_tile_x<MODE, BY, false, VK, NT>(A, md, mf, x0, y0, z0, z1, P);
 }
 
 // Tile order: tiles are numbered with x (or y) fastest, then the other

@@ -50,21 +50,24 @@ std::vector<TileCfg> tile_candidates(int mode, const Grid& g)
     const int bys[3] = {2, 4, 8};
     const int tzs[5] = {8, 16, 32, 64, 128};
     for (int by : bys)
-        for (int tz : tzs) {
-            TileCfg t;
-            t.by = by;
-            t.tz = tz;
-            if (tz > 2 * std::max(g.nz, 1) && tz != tzs[0]) continue;  // deeper than the grid adds nothing
-            if (tile_supported(mode, g, t)) c.push_back(t);
-        }
+        for (int tz : tzs)
+            for (bool stream : {true, false}) {
+                TileCfg t;
+                t.by = by;
+                t.tz = tz;
+                t.stream = stream;
+                if (tz > 2 * std::max(g.nz, 1) && tz != tzs[0]) continue;  // deeper than the grid adds nothing
+                if (tile_supported(mode, g, t)) c.push_back(t);
+            }
     return c;
 }
 
 // ---- on-disk cache of the results ----
-// Text file: a header "lbm3d-tune 1 <arch>" naming the device architecture
+// Text file: a header "lbm3d-tune 2 <arch>" naming the device architecture
 // the shapes were measured on, then one line per result:
-//   tile <precision> <nx> <ny> <nz> <bc -x> <bc +x> <bc -y> <bc +y> <bc -z> <bc +z> <by> <tz>
+//   tile <precision> <nx> <ny> <nz> <bc -x> <bc +x> <bc -y> <bc +y> <bc -z> <bc +z> <by> <tz> <stream>
 //   batch <precision> <tz>
+// (<stream>: 1 for non-temporal stores of the new level, 0 for plain ones.)
 
 std::string device_arch()
 {
@@ -81,11 +84,11 @@ int32_t save_locked(const char* path)
     const std::string tmp = std::string(path) + ".tmp";
     FILE* fp = std::fopen(tmp.c_str(), "w");
     if (!fp) return LBM3D_E_INVAL;
-    bool ok = std::fprintf(fp, "lbm3d-tune 1 %s\n", device_arch().c_str()) > 0;
+    bool ok = std::fprintf(fp, "lbm3d-tune 2 %s\n", device_arch().c_str()) > 0;
     for (const auto& kv : g_tiles) {
         const auto& v = kv.first.v;
-        ok = ok && std::fprintf(fp, "tile %d %d %d %d %d %d %d %d %d %d %d %d\n", v[0], v[1], v[2], v[3], v[4], v[5],
-                                v[6], v[7], v[8], v[9], kv.second.by, kv.second.tz) > 0;
+        ok = ok && std::fprintf(fp, "tile %d %d %d %d %d %d %d %d %d %d %d %d %d\n", v[0], v[1], v[2], v[3], v[4],
+                                v[5], v[6], v[7], v[8], v[9], kv.second.by, kv.second.tz, kv.second.stream ? 1 : 0) > 0;
     }
     for (int m = 0; m < 3; m++)
         if (g_batch_tz[m] > 0) ok = ok && std::fprintf(fp, "batch %d %d\n", m, g_batch_tz[m]) > 0;
@@ -106,14 +109,17 @@ int32_t load_locked(const char* path)
     char line[512], kind[16], arch[128];
     int version = 0;
     bool ok = std::fgets(line, sizeof line, fp) && std::sscanf(line, "lbm3d-tune %d %127s", &version, arch) == 2 &&
-              version == 1 && device_arch() == arch;
+              version == 2 && device_arch() == arch;
     while (ok && std::fgets(line, sizeof line, fp)) {
         if (std::sscanf(line, "%15s", kind) != 1) continue;  // blank line
         if (!std::strcmp(kind, "tile")) {
             ShapeKey k;
             TileCfg t;
-            ok = std::sscanf(line, "tile %d %d %d %d %d %d %d %d %d %d %d %d", &k.v[0], &k.v[1], &k.v[2], &k.v[3],
-                             &k.v[4], &k.v[5], &k.v[6], &k.v[7], &k.v[8], &k.v[9], &t.by, &t.tz) == 12;
+            int stream = -1;
+            ok = std::sscanf(line, "tile %d %d %d %d %d %d %d %d %d %d %d %d %d", &k.v[0], &k.v[1], &k.v[2], &k.v[3],
+                             &k.v[4], &k.v[5], &k.v[6], &k.v[7], &k.v[8], &k.v[9], &t.by, &t.tz, &stream) == 13;
+            ok = ok && (stream == 0 || stream == 1);
+            t.stream = stream == 1;
             ok = ok && k.v[0] >= 0 && k.v[0] <= 2 && k.v[1] >= 1 && k.v[2] >= 1 && k.v[3] >= 1;
             for (int f = 4; ok && f < 10; f++) ok = k.v[f] >= LBM3D_PERIODIC && k.v[f] <= LBM3D_REFLECT;
             ok = ok && (t.by == 0 || t.by == 2 || t.by == 4 || (t.by == 8 && k.v[0] != 0)) && t.tz >= 1 && t.tz <= 65535;
@@ -249,6 +255,7 @@ extern "C" int32_t lbm3d_tune(lbm3d_t h, int32_t launches, int32_t* by, int32_t*
             best = cands[c];
         }
     int32_t rc = lbm3d_set_tile(h, best.by, best.tz);
+    if (rc == LBM3D_OK) rc = lbm3d_set_streaming(h, best.stream ? 1 : 0);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_mu);

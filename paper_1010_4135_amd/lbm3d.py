@@ -85,6 +85,8 @@ def _load():
         "lbm3d_batch_tune": (I32, [ctypes.POINTER(P), I32, I32, ctypes.POINTER(I32)]),
         "lbm3d_batch_set_depth": (I32, [I32, I32]),
         "lbm3d_get_tile": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "lbm3d_set_streaming": (I32, [P, I32]),
+        "lbm3d_get_streaming": (I32, [P, ctypes.POINTER(I32)]),
         "lbm3d_sync": (I32, [P]),
         "lbm3d_stream_copy_rate": (I32, [I64, I32, D]),
         "lbm3d_admit": (I32, [PP, D, D, D, D, D, D]),
@@ -230,6 +232,16 @@ def lbm3d_get_tile(h):
     tz = ctypes.c_int32(0)
     _check(_lib.lbm3d_get_tile(h, ctypes.byref(by), ctypes.byref(tz)), "lbm3d_get_tile")
     return by.value, tz.value
+
+
+def lbm3d_set_streaming(h, streaming: bool):
+    _check(_lib.lbm3d_set_streaming(h, 1 if streaming else 0), "lbm3d_set_streaming")
+
+
+def lbm3d_get_streaming(h) -> bool:
+    v = ctypes.c_int32(0)
+    _check(_lib.lbm3d_get_streaming(h, ctypes.byref(v)), "lbm3d_get_streaming")
+    return bool(v.value)
 
 
 def lbm3d_tune(h, launches: int = 10):
@@ -463,6 +475,12 @@ class Solver:
 
     def get_tile(self):
         return lbm3d_get_tile(self.h)
+
+    def set_streaming(self, streaming: bool):
+        lbm3d_set_streaming(self.h, streaming)
+
+    def streaming(self) -> bool:
+        return lbm3d_get_streaming(self.h)
 
     def tune(self, launches: int = 10):
         return lbm3d_tune(self.h, launches)

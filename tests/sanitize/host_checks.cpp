@@ -118,10 +118,10 @@ int main(int argc, char** argv)
     const std::string good = tmp + "/tune_good.txt", bad = tmp + "/tune_bad.txt", out = tmp + "/tune_out.txt";
     {
         FILE* fp = std::fopen(good.c_str(), "w");
-        std::fprintf(fp, "lbm3d-tune 1 none\ntile 2 256 128 128 2 1 3 3 3 3 8 32\nbatch 1 64\n");
+        std::fprintf(fp, "lbm3d-tune 2 none\ntile 2 256 128 128 2 1 3 3 3 3 8 32 1\nbatch 1 64\n");
         std::fclose(fp);
         fp = std::fopen(bad.c_str(), "w");
-        std::fprintf(fp, "lbm3d-tune 1 none\ntile 2 256 128 128 2 1 3 3 3 3 8 32 9 9 9 9 9 9 9 9\nbatch 7 1\n");
+        std::fprintf(fp, "lbm3d-tune 2 none\ntile 2 256 128 128 2 1 3 3 3 3 8 32 1 9 9 9 9 9 9 9 9\nbatch 7 1\n");
         std::fclose(fp);
     }
     EXPECT(lbm3d_tune_load(good.c_str()) == LBM3D_OK);

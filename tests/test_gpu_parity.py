@@ -344,6 +344,36 @@ def test_results_do_not_depend_on_tile_shape(precision, which):
             assert np.array_equal(f, ref), (by, tz)
 
 
+def test_store_kind_defaults_and_changes_no_result():
+    """The tiled step stores the new level plainly for solves whose two
+    levels fit in 320 MB and non-temporally for larger ones; either kind, at
+    either tile shape, gives bitwise the same distributions."""
+    lbm3d = _lib()
+    big = inputs.shock_bubble(0, precision="fp32_t64")  # 256x128x128: 0.5 GB for both levels
+    s = lbm3d.Solver(dict(big.params))
+    assert s.streaming()
+    s.close()
+    case = inputs.shock_bubble(21, grid=(70, 19, 13), precision="fp32_t64", mach=4.0, ratio=0.4)
+    ref = None
+    for by, tz in ((8, 4), (4, 16)):
+        for streaming in (False, True):
+            s = lbm3d.Solver(dict(case.params))
+            assert not s.streaming()
+            s.set_tile(by, tz)
+            s.set_streaming(streaming)
+            assert s.streaming() == streaming and s.get_tile() == (by, tz)
+            s.init(*case.fields)
+            s.step(13)
+            f = s.get_f()
+            s.close()
+            if ref is None:
+                ref = f
+            assert np.array_equal(f, ref), (by, tz, streaming)
+    s = lbm3d.Solver(dict(case.params))
+    assert lbm3d._lib.lbm3d_set_streaming(s.h, 2) == lbm3d.E_INVAL  # (the binding passes 0 or 1)
+    s.close()
+
+
 def test_switching_launch_shape_mid_run():
     """A tiled run that hands over to the untiled kernel part way (layers the
     tiles formed themselves are refreshed in memory) matches an untiled run."""
@@ -376,7 +406,7 @@ def test_autotuner_keeps_state_and_is_remembered():
     assert np.array_equal(a.get_f(), f5)
     a.step(12)
     b = lbm3d.Solver(dict(case.params))
-    assert b.get_tile() == (by, tz)
+    assert b.get_tile() == (by, tz) and b.streaming() == a.streaming()
     b.set_tile(0, 1)
     b.init(*case.fields)
     b.step(17)
@@ -576,8 +606,8 @@ def test_tune_cache_on_disk(tmp_path):
     path = tmp_path / "tune.txt"
     lbm3d.lbm3d_tune_save(str(path))
     lines = path.read_text().splitlines()
-    assert lines[0].startswith("lbm3d-tune 1 gfx")
-    assert f"tile 2 128 40 24 2 1 3 3 3 3 {by} {tz}" in lines
+    assert lines[0].startswith("lbm3d-tune 2 gfx")
+    assert any(line.startswith(f"tile 2 128 40 24 2 1 3 3 3 3 {by} {tz} ") for line in lines)
     # a child process tunes with the cache variable set; the next one reads it
     env = dict(os.environ, LBM3D_TUNE_CACHE=str(tmp_path / "env.txt"))
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -587,8 +617,9 @@ def test_tune_cache_on_disk(tmp_path):
             "s = lbm3d.Solver(c.params)\n"
             "if sys.argv[1] == 'tune':\n"
             "    s.init(*c.fields); print(*s.tune(3))\n"
+            "    print(int(s.streaming()))\n"
             "else:\n"
-            "    print(*s.get_tile())\n") % root
+            "    print(*s.get_tile()); print(int(s.streaming()))\n") % root
     t = subprocess.run([sys.executable, "-c", prog, "tune"], env=env, capture_output=True, text=True, timeout=120)
     assert t.returncode == 0, t.stderr
     r = subprocess.run([sys.executable, "-c", prog, "read"], env=env, capture_output=True, text=True, timeout=120)

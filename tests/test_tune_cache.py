@@ -25,16 +25,16 @@ pytestmark = pytest.mark.skipif(_arch() is None, reason="host-side cache tests r
 def test_round_trip(tmp_path):
     lbm3d = _lib()
     src = tmp_path / "a.txt"
-    src.write_text("lbm3d-tune 1 none\n"
-                   "tile 2 256 128 128 2 1 3 3 3 3 8 32\n"
-                   "tile 0 128 128 128 0 0 0 0 0 0 4 64\n"
+    src.write_text("lbm3d-tune 2 none\n"
+                   "tile 2 256 128 128 2 1 3 3 3 3 8 32 1\n"
+                   "tile 0 128 128 128 0 0 0 0 0 0 4 64 0\n"
                    "batch 1 64\n")
     lbm3d.lbm3d_tune_load(str(src))
     out = tmp_path / "b.txt"
     lbm3d.lbm3d_tune_save(str(out))
     lines = out.read_text().splitlines()
-    assert lines[0] == "lbm3d-tune 1 none"
-    for want in ("tile 2 256 128 128 2 1 3 3 3 3 8 32", "tile 0 128 128 128 0 0 0 0 0 0 4 64", "batch 1 64"):
+    assert lines[0] == "lbm3d-tune 2 none"
+    for want in ("tile 2 256 128 128 2 1 3 3 3 3 8 32 1", "tile 0 128 128 128 0 0 0 0 0 0 4 64 0", "batch 1 64"):
         assert want in lines
     assert not os.path.exists(str(out) + ".tmp")
 
@@ -42,12 +42,12 @@ def test_round_trip(tmp_path):
 def test_loaded_batch_depth_reaches_the_plan(tmp_path):
     lbm3d = _lib()
     src = tmp_path / "c.txt"
-    src.write_text("lbm3d-tune 1 none\nbatch 1 16\n")
+    src.write_text("lbm3d-tune 2 none\nbatch 1 16\n")
     lbm3d.lbm3d_tune_load(str(src))
     p = inputs.make_params((64, 8, 48), (0,) * 6, precision="fp32")
     tiles, _, _ = lbm3d.lbm3d_batch_plan([p], tz=0, cus=256)
     assert set((tiles[:, 6] - tiles[:, 5]).tolist()) == {16}
-    src.write_text("lbm3d-tune 1 none\nbatch 1 48\n")
+    src.write_text("lbm3d-tune 2 none\nbatch 1 48\n")
     lbm3d.lbm3d_tune_load(str(src))
     tiles, _, _ = lbm3d.lbm3d_batch_plan([p], tz=0, cus=256)
     assert set((tiles[:, 6] - tiles[:, 5]).tolist()) == {48}
@@ -56,14 +56,17 @@ def test_loaded_batch_depth_reaches_the_plan(tmp_path):
 
 @pytest.mark.parametrize("text", [
     "",                                              # no header
-    "lbm3d-tune 2 none\n",                           # unknown version
-    "lbm3d-tune 1 gfx950\n",                         # another architecture
-    "lbm3d-tune 1 none\ntile 2 256 128 128 2 1 3 3 3 3 7 32\n",   # no such tile height
-    "lbm3d-tune 1 none\ntile 0 256 128 128 2 1 3 3 3 3 8 32\n",   # 8-row tiles are FP32 only
-    "lbm3d-tune 1 none\ntile 2 256 128 128 2 1 3 3 3 9 8 32\n",   # no such boundary kind
-    "lbm3d-tune 1 none\nbatch 3 16\n",               # no such precision
-    "lbm3d-tune 1 none\nbatch 1 0\n",
-    "lbm3d-tune 1 none\nsomething 1 2\n",
+    "lbm3d-tune 1 none\n",                           # an older format (no store kinds)
+    "lbm3d-tune 3 none\n",                           # unknown version
+    "lbm3d-tune 2 gfx950\n",                         # another architecture
+    "lbm3d-tune 2 none\ntile 2 256 128 128 2 1 3 3 3 3 7 32 1\n",   # no such tile height
+    "lbm3d-tune 2 none\ntile 0 256 128 128 2 1 3 3 3 3 8 32 1\n",   # 8-row tiles are FP32 only
+    "lbm3d-tune 2 none\ntile 2 256 128 128 2 1 3 3 3 9 8 32 1\n",   # no such boundary kind
+    "lbm3d-tune 2 none\ntile 2 256 128 128 2 1 3 3 3 3 8 32 2\n",   # no such store kind
+    "lbm3d-tune 2 none\ntile 2 256 128 128 2 1 3 3 3 3 8 32\n",     # store kind missing
+    "lbm3d-tune 2 none\nbatch 3 16\n",               # no such precision
+    "lbm3d-tune 2 none\nbatch 1 0\n",
+    "lbm3d-tune 2 none\nsomething 1 2\n",
 ])
 def test_bad_files_are_refused_and_change_nothing(tmp_path, text):
     lbm3d = _lib()
