@@ -223,6 +223,11 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     if (members.empty()) return LBM3D_OK;
     mode_ = members[0]->mode;
     by_ = mode_ == LBM3D_FP64 ? 4 : 8;
+    // plain stores when the members' levels together fit the memory-side
+    // cache, as for a single solve
+    int64_t level_bytes = 0;
+    for (lbm3d_solver* h : members) level_bytes += 2 * (int64_t)f_bytes(h->g, h->mode);
+    stream_ = level_bytes > STREAM_MIN_BYTES;
     tz_ = plan_depth(mode_, tz);
     std::vector<Grid> grids;
     for (lbm3d_solver* h : members) grids.push_back(h->g);
@@ -309,7 +314,8 @@ hipError_t BatchPlan::launch_at(int parity, hipStream_t s)
 
 hipError_t BatchPlan::enqueue(int parity, hipStream_t s)
 {
-    hipError_t e = launch_batch_step(mode_, by_, dsolves_, dtiles_, dqueue_, plan_.nlists, plan_.nblocks, parity, s);
+    hipError_t e = launch_batch_step(mode_, by_, stream_, dsolves_, dtiles_, dqueue_, plan_.nlists, plan_.nblocks,
+                                     parity, s);
     if (e != hipSuccess) return e;
     // boundary layers the tiles do not form themselves, all members at once
     return launch_batch_layers(mode_, dsolves_, dlayers_, dblockjob_, nlblocks_, parity, s);

@@ -66,6 +66,7 @@ private:
 
     std::vector<lbm3d_solver*> members_;
     int mode_ = 0, by_ = 8, tz_ = 8;
+    bool stream_ = true;  // non-temporal stores (the members' levels exceed STREAM_MIN_BYTES)
     TilePlan plan_;
     void* dmem_ = nullptr;  // tables allocated by the plan (nullptr with a caller's buffer)
     size_t dbytes_ = 0;

@@ -144,7 +144,7 @@ __device__ __forceinline__ void keep_model(Model<T>& m)
     keep(m.k_adv); keep(m.k_bgk); keep(m.k_lap0); keep(m.k_lap1); keep(m.a1); keep(m.ad);
 }
 
-template <int MODE, int BY>
+template <int MODE, int BY, bool NT>
 __global__ void __launch_bounds__(TILE_X * BY)
 k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict__ tiles, BatchQueue* queue,
              int nlists, int parity)
@@ -190,8 +190,7 @@ k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict_
         keep(A.g.sy); keep(A.g.sz); keep(A.g.sv); keep(A.g.org); keep(A.g.sink); keep(A.g.xg);
         keep(A.f); keep(A.fn);
         keep_model(mf);
-        // (streaming stores: a batch's levels are far larger than the caches)
-        step_tile<MODE, BY, true, true>(A, md, mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
+        step_tile<MODE, BY, true, NT>(A, md, mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
         lds_barrier();  // the plane buffers (and s_k) are reused by the next tile
     }
 }
@@ -606,21 +605,26 @@ hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLa
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles,
+template <int MODE, int BY>
+static void launch_batch(unsigned nblocks, bool stream, const BatchSolve* solves, const BatchTile* tiles,
+                         BatchQueue* queue, int nlists, int parity, hipStream_t s)
+{
+    if (stream)
+        k_batch_step<MODE, BY, true><<<dim3(nblocks), dim3(TILE_X * BY), 0, s>>>(solves, tiles, queue, nlists, parity);
+    else
+        k_batch_step<MODE, BY, false><<<dim3(nblocks), dim3(TILE_X * BY), 0, s>>>(solves, tiles, queue, nlists, parity);
+}
+
+hipError_t launch_batch_step(int mode, int by, bool stream, const BatchSolve* solves, const BatchTile* tiles,
                              BatchQueue* queue, int nlists, int nblocks, int parity, hipStream_t s)
 {
     if (nblocks <= 0 || nlists <= 0 || nlists > BATCH_MAX_LISTS || nblocks % nlists) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)nblocks);
-    switch (by) {
-    case 2: LBM3D_DISPATCH(mode, k_batch_step<MD, 2><<<grid, dim3(TILE_X * 2), 0, s>>>(solves, tiles, queue, nlists, parity)); break;
-    case 8:
-        if (mode == MODE_FP64) return hipErrorInvalidValue;
-        if (mode == MODE_FP32) k_batch_step<MODE_FP32, 8><<<grid, dim3(TILE_X * 8), 0, s>>>(solves, tiles, queue, nlists, parity);
-        else k_batch_step<MODE_FP32_T64, 8><<<grid, dim3(TILE_X * 8), 0, s>>>(solves, tiles, queue, nlists, parity);
-        break;
-    case 4: LBM3D_DISPATCH(mode, k_batch_step<MD, 4><<<grid, dim3(TILE_X * 4), 0, s>>>(solves, tiles, queue, nlists, parity)); break;
-    default: return hipErrorInvalidValue;
-    }
+    // the batch's tile heights: 4 rows in FP64, 8 in the FP32 modes
+    if (by != (mode == MODE_FP64 ? 4 : 8)) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)nblocks;
+    if (mode == MODE_FP64) launch_batch<MODE_FP64, 4>(nb, stream, solves, tiles, queue, nlists, parity, s);
+    else if (mode == MODE_FP32) launch_batch<MODE_FP32, 8>(nb, stream, solves, tiles, queue, nlists, parity, s);
+    else launch_batch<MODE_FP32_T64, 8>(nb, stream, solves, tiles, queue, nlists, parity, s);
     return hipGetLastError();
 }
 

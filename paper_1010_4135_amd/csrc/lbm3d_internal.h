@@ -144,8 +144,9 @@ hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLa
 // out[k] = the health word of member k (n members).
 hipError_t launch_gather_health(const BatchSolve* solves, int n, uint32_t* out, hipStream_t s);
 // One step of every member: `nblocks` persistent workgroups (a multiple of
-// `nlists`); workgroup b works on list b mod nlists.
-hipError_t launch_batch_step(int mode, int by, const BatchSolve* solves, const BatchTile* tiles,
+// `nlists`); workgroup b works on list b mod nlists.  `stream`: the store
+// kind of the new level (see STREAM_MIN_BYTES).
+hipError_t launch_batch_step(int mode, int by, bool stream, const BatchSolve* solves, const BatchTile* tiles,
                              BatchQueue* queue, int nlists, int nblocks, int parity, hipStream_t s);
 
 // block shape of the untiled step kernel; x extent of a tile of the tiled one;
