@@ -4,9 +4,11 @@ For each of the light bubble and the heavy droplet: the interior 298 x 78 x
 78 grid of the paper's (0:301, 0:81, 0:81) nodes, (c1, c2, eta0) = (2, 6,
 4), dx = 0.001, dt = tau = 1e-5, 10000 steps (t = 0.1), run in FP64 and in
 FP32 with FP64 moments and equilibrium.  Reports the stability admission,
-the autotuned launch shape, health, the change of the domain totals (the faces are open, so the totals
-move by the fluxes through them), the FP32 run's relative L1 distance to
-the FP64 run per field, and the time; writes the density on the paper's
+the autotuned launch shape and store kind, health, the change of the domain
+totals (the faces are open, so the totals move by the fluxes through them:
+relative change of mass and energy, change of each momentum component per
+unit of initial mass), the FP32 run's relative L1 distance to the FP64 run
+per field, and the time; writes the density on the paper's
 section z = 40 (interior plane 38) at t = 0.1 of every run to
 <out>/<kind>_<precision>_z40.npy and a JSON summary to <out>/summary.json.
 
@@ -37,17 +39,20 @@ def run(out_dir: str, steps: int = 10000, kinds=("bubble", "droplet"), precision
             with lbm3d.Solver(prm) as s:
                 s.init(*case.fields)
                 tile = s.tune()  # launch shape for this grid (the state is unchanged)
+                stores = "non-temporal" if s.streaming() else "plain"
                 c0 = s.conserved()
                 ms = s.step_timed(steps)
                 health, done = s.status()
                 m = s.moments(allow_nonfinite=True)
                 c1 = s.conserved()
+            mass0 = float(c0[0])
             row = {"admission": {"status": lbm3d.lbm3d_strerror(rc), "max_omega": round(om, 6)}, "tile": list(tile),
-                   "health": health, "steps_done": done, "device_ms": round(ms, 2),
+                   "stores": stores, "health": health, "steps_done": done, "device_ms": round(ms, 2),
                    "mlups": round(case.sites * steps / (ms / 1e3) / 1e6, 1),
                    "totals_t0": [float(v) for v in c0], "totals_end": [float(v) for v in c1],
-                   "relative_change_of_totals": [float((b - a) / abs(a)) if a else float(b - a)
-                                                 for a, b in zip(c0, c1)]}
+                   "change_of_totals": {"mass_relative": float((c1[0] - c0[0]) / c0[0]),
+                                        "momentum_per_initial_mass": [float((c1[k] - c0[k]) / mass0) for k in (1, 2, 3)],
+                                        "energy_relative": float((c1[4] - c0[4]) / c0[4])}}
             if prec == "fp64":
                 ref = m
             elif ref is not None:
