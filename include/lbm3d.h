@@ -168,7 +168,7 @@ int32_t lbm3d_get_tile(lbm3d_t h, int32_t* by, int32_t* tz);
 
 /* Store kind of the tiled kernels' new level: 1 = non-temporal (streaming
  * past the caches), 0 = plain.  A solve starts with plain stores when its
- * two distribution levels fit in 320 MB (the next step then reads much of
+ * two distribution levels fit in 320 MiB (the next step then reads much of
  * its input from the 256 MB memory-side cache), else with non-temporal
  * ones; the autotuner picks it with the shape.  Results are bitwise
  * independent of it; the untiled kernel always stores plainly and the
