@@ -25,8 +25,9 @@ Beside it:
                 FP32 modes' per-field error against the FP64 run;
   periodic_riemann  the 128^3 periodic 3D Riemann problem over its 1000
                 steps in FP64, FP32 and FP32 with FP64 moments and
-                equilibrium: MLUPS, kernel GB/s and the FP32 modes' error
-                against the FP64 run;
+                equilibrium: MLUPS, kernel GB/s, the drift of the
+                conserved totals and the FP32 modes' error against the
+                FP64 run;
   batch         64 solves of uneven size, 500 steps each, in one persistent
                 launch per step vs the same solves stepped one after another,
                 and vs the plain one-at-a-time FP64 loop (with the batched
@@ -233,11 +234,22 @@ def batch_bench(lbm3d, inputs, metrics, seed: int, count: int = 64, steps: int =
             "max_rel_l1_batched_vs_fp64": float(f"{err:.3e}")}
 
 
+def conservation_drift(c0, c1) -> dict:
+    """Change of the domain totals (mass, momentum, energy) between two
+    reads: mass and energy relative to their first value, the largest
+    momentum component's change per unit of the first mass (a velocity)."""
+    return {"mass_relative": float(f"{(c1[0] - c0[0]) / c0[0]:.3e}"),
+            "momentum_per_mass": float(f"{np.abs(c1[1:4] - c0[1:4]).max() / c0[0]:.3e}"),
+            "energy_relative": float(f"{(c1[4] - c0[4]) / c0[4]:.3e}")}
+
+
 def periodic_riemann_bench(lbm3d, inputs, metrics, seed: int, steps: int = 1000):
     """128^3 periodic 3D Riemann problem in each precision: MLUPS, the step
-    kernel's algorithmic GB/s, and the FP32 modes' per-field relative L1
-    distance to the FP64 run after the same steps (the FP64 mode itself is
-    held to the FP64 oracle by the parity tests)."""
+    kernel's algorithmic GB/s, the drift of the conserved totals over the
+    run (on a periodic box every flux telescopes, so only rounding moves
+    them), and the FP32 modes' per-field relative L1 distance to the FP64
+    run after the same steps (the FP64 mode itself is held to the FP64
+    oracle by the parity tests)."""
     out = {"workload": "riemann_3d 128^3 periodic", "steps": steps}
     ref = None
     for prec in ("fp64", "fp32", "fp32_t64"):
@@ -245,13 +257,16 @@ def periodic_riemann_bench(lbm3d, inputs, metrics, seed: int, steps: int = 1000)
         s = lbm3d.Solver(case.params)
         s.init(*case.fields)
         s.tune(5)
+        c0 = s.conserved()
         ms = s.step_timed(steps)
+        c1 = s.conserved()
         m = s.moments()  # after exactly `steps` steps in every precision
         _, kms = s.step_profiled(20)
         bps = BYTES_PER_SITE[prec]
         s.close()
         row = {"mlups": round(case.sites * steps / (ms / 1e3) / 1e6, 1),
-               "kernel_gbs": round(case.sites * bps / (kms / 1e3) / 1e9, 1)}
+               "kernel_gbs": round(case.sites * bps / (kms / 1e3) / 1e9, 1),
+               "conservation_drift": conservation_drift(c0, c1)}
         if prec == "fp64":
             ref = m
         else:
