@@ -76,6 +76,7 @@ def _load():
         lib.orc_get_f_padded.argtypes = [P, D]
         lib.orc_steps_done.restype = ctypes.c_int64
         lib.orc_steps_done.argtypes = [P]
+        lib.orc_nonphysical.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
         lib.orc_velocities.argtypes = [ctypes.c_double] * 3 + [D, D]
         lib.orc_equilibrium.argtypes = [ctypes.c_double] * 9 + [D]
         lib.orc_moments_of.argtypes = [ctypes.c_double] * 4 + [D, D]
@@ -171,6 +172,13 @@ class Oracle:
     @property
     def steps_done(self) -> int:
         return int(self._lib.orc_steps_done(self._h))
+
+    def nonphysical(self):
+        """(node-steps with rho <= 0, node-steps with T <= 0) since init,
+        counted at the state each step starts from."""
+        out = (ctypes.c_int64 * 2)()
+        self._lib.orc_nonphysical(self._h, out)
+        return int(out[0]), int(out[1])
 
     def moments(self):
         """(rho, ux, uy, uz, p) arrays of shape (nz, ny, nx)."""

@@ -64,6 +64,9 @@ typedef struct {
     int64_t mx, my, mz;
     double *f, *fn;
     int64_t steps;
+    /* node-steps, since init, whose state at level n had rho <= 0 and
+     * T <= 0 (NaN counts in both): a diagnostic, not part of the scheme */
+    int64_t nonpos_rho, nonpos_T;
 } orc_state;
 
 /* ---------------------------------------------------------------- model -- */
@@ -265,13 +268,16 @@ static void step_once(orc_state* s)
     const int64_t stride[3] = {1, s->mx, s->mx * s->my};
     const double* f = s->f;
     double* fn = s->fn;
-#pragma omp parallel for collapse(3) schedule(static)
+    int64_t bad_rho = 0, bad_T = 0;
+#pragma omp parallel for collapse(3) schedule(static) reduction(+ : bad_rho, bad_T)
     for (int64_t z = 0; z < p->nz; z++) {
         for (int64_t y = 0; y < p->ny; y++) {
             for (int64_t x = 0; x < p->nx; x++) {
                 double fs[NV], q[5], feq[NV];
                 site_f(s, f, x, y, z, fs);
                 moments((const double(*)[3])s->v, s->eta, s->b, fs, q);
+                if (!(q[0] > 0.0)) bad_rho++;
+                if (!(q[4] > 0.0)) bad_T++;
                 equilibrium((const double(*)[3])s->v, p->c1, p->c2, p->eta0, s->b,
                             q[0], q[1], q[2], q[3], q[4], feq);
                 for (int i = 0; i < NV; i++) {
@@ -324,6 +330,8 @@ static void step_once(orc_state* s)
     s->fn = t;
     fill_boundaries(s, s->f);
     s->steps++;
+    s->nonpos_rho += bad_rho;
+    s->nonpos_T += bad_T;
 }
 
 /* ------------------------------------------------------------- exports -- */
@@ -379,6 +387,8 @@ void orc_init(orc_state* s, const double* rho, const double* ux, const double* u
             }
     fill_boundaries(s, s->f);
     s->steps = 0;
+    s->nonpos_rho = 0;
+    s->nonpos_T = 0;
 }
 
 void orc_step(orc_state* s, int64_t nsteps)
@@ -455,6 +465,15 @@ void orc_get_f_padded(const orc_state* s, double* out)
 }
 
 int64_t orc_steps_done(const orc_state* s) { return s->steps; }
+
+/* Node-steps since init that started from a state with rho <= 0 (out[0])
+ * and with T <= 0 (out[1]), counted on the interior nodes at the moments
+ * each step recovers from f^n. */
+void orc_nonphysical(const orc_state* s, int64_t out[2])
+{
+    out[0] = s->nonpos_rho;
+    out[1] = s->nonpos_T;
+}
 
 /* Stand-alone model functions, exposed for the checks. */
 void orc_velocities(double c1, double c2, double eta0, double v[NV][3], double eta[NV])

@@ -125,7 +125,8 @@ def test_quasi_1d_riemann_256x4x4_fp64_500_steps():
 
 def test_periodic_riemann_128cubed_fp64_full_grid():
     """128^3 periodic 3D Riemann problem at full size: 8 steps element by
-    element (the oracle is too slow for the full 1000 at this size)."""
+    element (the full 1000 steps take the oracle minutes; they run in
+    test_gpu_full_length.py when asked for)."""
     case = inputs.riemann_3d(1)
     s, mg = gpu_run(case, 8)
     o, mo = oracle_run(case, 8)

@@ -568,3 +568,25 @@ def test_upwind2_oscillates_more_than_nnd_on_the_lax_tube():
         assert np.all(np.isfinite(rho))
         excess[name] = np.abs(np.diff(rho)).sum() - tv_exact
     assert excess["upwind2"] > 3.0 * max(excess["nnd"], 1e-3 * tv_exact), excess
+
+
+def test_nonphysical_state_counts():
+    """The oracle's diagnostic count of node-steps starting from rho <= 0 or
+    T <= 0: zero on a uniform state; on a box with one node at T < 0 and one
+    at rho < 0 (and so T = p / rho < 0), the first step counts exactly
+    (1, 2), since it starts from the initial state whose moments are the
+    given fields (the equilibrium's moments, Eqs. (e1)-(e3))."""
+    grid = (6, 5, 4)
+    prm = inputs.make_params(grid, (inputs.PERIODIC,) * 6)
+    shape = grid[::-1]
+    rho, ux, uy, uz, p = (np.ones(shape), np.zeros(shape), np.zeros(shape), np.zeros(shape), np.ones(shape))
+    o = oracle.Oracle(prm)
+    o.init(rho, ux, uy, uz, p)
+    o.step(3)
+    assert o.nonphysical() == (0, 0)
+    p[1, 2, 3] = -0.5
+    rho[2, 3, 4], p[2, 3, 4] = -0.2, 0.1
+    o.init(rho, ux, uy, uz, p)
+    assert o.nonphysical() == (0, 0)
+    o.step(1)
+    assert o.nonphysical() == (1, 2)
