@@ -64,7 +64,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, vendor figure
 BYTES_PER_SITE = {"fp64": 240, "fp32": 120, "fp32_t64": 120}  # 15 reads + 15 writes of f
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_hbm_traffic.txt")
-KERNEL_SOURCES = ["lbm3d_tile.h", "lbm3d_model.h", "lbm3d_device.hip", "lbm3d_internal.h"]
+KERNEL_SOURCES = ["lbm3d_tile.h", "lbm3d_model.h", "lbm3d_device.hip", "lbm3d_internal.h", "lbm3d_layout.cpp"]
 
 
 def kernel_source_hash() -> str:

@@ -73,7 +73,11 @@ enum {
     LBM3D_UPWIND2 = 2u,        /* convection by the second-order upwind difference of the original scheme
                                   (Sec. 3, opening paragraph; Fig. 6) instead of NND: steps run untiled, and
                                   the batched step and servers refuse such solves */
-    LBM3D_CHECK_STABILITY = 4u /* lbm3d_init refuses (E_UNSTABLE) an initial state lbm3d_admit refuses */
+    LBM3D_CHECK_STABILITY = 4u,/* lbm3d_init refuses (E_UNSTABLE) an initial state lbm3d_admit refuses */
+    LBM3D_VELOCITY_MAJOR = 8u  /* store each level velocity by velocity (15 blocks of z planes) even where
+                                  it is below 2 GiB; by default such levels are stored plane by plane
+                                  (the 15 velocity planes of one z side by side), which the tiled step
+                                  streams faster.  Results are bitwise the same either way. */
 };
 
 /* health bits reported by lbm3d_status (sticky since init) */
@@ -94,7 +98,7 @@ typedef struct {
     int32_t bc[6];        /* faces -x, +x, -y, +y, -z, +z: LBM3D_PERIODIC .. LBM3D_REFLECT */
     double inflow[6][5];  /* (rho, ux, uy, uz, p) per LBM3D_INFLOW face; ignored elsewhere */
     int32_t precision;    /* LBM3D_FP64, LBM3D_FP32 or LBM3D_FP32_T64 */
-    uint32_t flags;       /* LBM3D_NO_DISSIPATION | LBM3D_UPWIND2 | LBM3D_CHECK_STABILITY */
+    uint32_t flags;       /* LBM3D_NO_DISSIPATION | LBM3D_UPWIND2 | LBM3D_CHECK_STABILITY | LBM3D_VELOCITY_MAJOR */
 } lbm3d_params;
 
 typedef struct lbm3d_solver* lbm3d_t;

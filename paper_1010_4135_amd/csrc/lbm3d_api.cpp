@@ -40,7 +40,8 @@ int32_t validate(const lbm3d_params* p)
     if (!std::isfinite(p->gamma) || !(p->gamma > 1.0)) return LBM3D_E_INVAL;
     if (!finite_pos(p->tau) || !finite_pos(p->dt) || !finite_pos(p->dx)) return LBM3D_E_INVAL;
     if (p->precision < LBM3D_FP64 || p->precision > LBM3D_FP32_T64) return LBM3D_E_INVAL;
-    if (p->flags & ~(uint32_t)(LBM3D_NO_DISSIPATION | LBM3D_UPWIND2 | LBM3D_CHECK_STABILITY)) return LBM3D_E_INVAL;
+    if (p->flags & ~(uint32_t)(LBM3D_NO_DISSIPATION | LBM3D_UPWIND2 | LBM3D_CHECK_STABILITY | LBM3D_VELOCITY_MAJOR))
+        return LBM3D_E_INVAL;
     for (int face = 0; face < 6; face++) {
         if (p->bc[face] != LBM3D_INFLOW) continue;
         const double* s = p->inflow[face];
@@ -110,51 +111,6 @@ Model<float> model_to_float(const Model<double>& d)
     return f;
 }
 
-size_t elem_size(int precision) { return precision == LBM3D_FP64 ? 8 : 4; }
-
-// Padded layout: each x row holds `ox` leading elements (the two boundary
-// layers sit just before interior x = 0, which starts on a 128-byte line),
-// the nx interior nodes and two boundary layers, rounded up to whole lines.
-Grid make_grid(const lbm3d_params* p)
-{
-    Grid g;
-    const int64_t line = 128 / (int64_t)elem_size(p->precision);
-    g.nx = p->nx;
-    g.ny = p->ny;
-    g.nz = p->nz;
-    const bool dense = dense_rows(p->nx);
-    // dense rows: the interior only, rows start on a line (nx is a multiple
-    // of 64 elements); otherwise the x layers pad the rows
-    const int64_t ox = dense ? 0 : line;
-    // one cache line of padding per row, holding the two right layer nodes
-    // of the row (its first elements) and the two left layer nodes of the
-    // next row (its last elements); interior rows start on a line
-    const int64_t mxp = (p->nx + line - 1) / line * line + line;
-    const int64_t mx = dense ? p->nx : mxp;
-    const int64_t my = p->ny + 2 * NG;
-    const int64_t mz = p->nz + 2 * NG;
-    g.my = (int32_t)my;
-    g.sy = mx;
-    g.sz = mx * my;
-    // the sink region of the tiled step's stores from lanes outside the
-    // grid, after one spare line (the right layer nodes of the last row of a
-    // padded array reach two elements past sz * mz)
-    g.sink = g.sz * mz + line;
-    const int64_t sink_end = g.sink + (int64_t)SINK_ROWS * TILE_X;
-    // dense rows: the x layers of every row (4 nodes) after the sink region
-    g.xg = dense ? sink_end + line : 0;
-    const int64_t end = dense ? g.xg + 4 * my * mz : sink_end + line;
-    // velocity planes are separated by an odd number of 256-byte blocks so
-    // that the 15 streams do not start on the same memory channel
-    const int64_t blk = 256 / (int64_t)elem_size(p->precision);
-    int64_t sv = (end + blk - 1) / blk;
-    if ((sv & 1) == 0) sv += 1;
-    g.sv = sv * blk;
-    g.org = NG * g.sz + NG * g.sy + ox;
-    return g;
-}
-
-size_t f_bytes(const Grid& g, int precision) { return (size_t)NV * (size_t)g.sv * elem_size(precision); }
 
 size_t footprint_of(const lbm3d_params* p)
 {

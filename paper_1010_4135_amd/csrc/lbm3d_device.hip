@@ -67,7 +67,7 @@ __device__ __forceinline__ void update_all(const S* __restrict__ f, S* __restric
 __device__ __forceinline__ void x_offsets(const Grid& g, int x, int y, int z, int64_t site, int64_t (&xo)[4])
 {
     const int d[4] = {-2, -1, 1, 2};
-    const int64_t row = g.xg + ((int64_t)(z + NG) * g.my + (y + NG)) * 4;
+    const int64_t row = g.xg + (int64_t)(z + NG) * g.xgz + (int64_t)(y + NG) * 4;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const int xx = x + d[k];
@@ -280,7 +280,7 @@ __device__ __forceinline__ void layer_job(const StepArgs<MODE>& A, const Model<d
         uint32_t l1 = line + (uint32_t)(side ? n : -1) * st;
         uint32_t l2 = line + (uint32_t)(side ? n + 1 : -2) * st;
         if (axis == 0 && g.xg != 0) {
-            const uint32_t row = (uint32_t)(g.xg + ((int64_t)(cz + NG) * g.my + (cy + NG)) * 4);
+            const uint32_t row = (uint32_t)(g.xg + (int64_t)(cz + NG) * g.xgz + (int64_t)(cy + NG) * 4);
             l1 = row + (side ? 2u : 1u);
             l2 = row + (side ? 3u : 0u);
         }

@@ -30,20 +30,35 @@ struct Model {
     T a1, ad;            // dt/dx c1 and dt/dx c2/sqrt(3): advection factors per axis
 };
 
-// Geometry of one solve's padded distribution array f[15][mz][my][mx]:
-// interior node (x, y, z) of velocity i sits at i*sv + org + z*sz + y*sy + x.
-// Two boundary layers pad each face.  The y and z layers are rows and
-// planes of the array.  The x layers either sit in the row padding (xg = 0)
-// or, when the rows are dense (mx = nx), in a block of their own per
-// velocity plane: layer k (0: x = -2, 1: x = -1, 2: x = nx, 3: x = nx+1) of
-// row (y, z) at xg + ((z + 2) * my + y + 2) * 4 + k.
+// Geometry of one solve's padded distribution array: interior node
+// (x, y, z) of velocity i sits at i*sv + org + z*sz + y*sy + x.  Two
+// boundary layers pad each face; the y and z layers are rows and planes of
+// the array.  The planes are ordered one of two ways:
+//  - plane-major, f[mz][15][my][mx] (every level below 2 GiB): the 15
+//    velocity planes of one z lie side by side (sv = plane stride,
+//    sz = 15 sv), so a tile marching z reads and writes one compact region
+//    per plane step rather than 15 regions a velocity block apart, which
+//    the memory streams measurably faster;
+//  - velocity-major, f[15][mz][my][mx] (larger levels): each velocity's
+//    planes form one block (sz = plane, sv = block), so that everything the
+//    tiled kernels reach from a velocity's base stays within 32-bit offsets.
+// Plane (plane-major) and block (velocity-major) strides are odd numbers of
+// 256-byte blocks, so that the 15 streams do not start on the same memory
+// channel.  The x layers either sit in the row padding (xg = 0) or, when
+// the rows are dense (mx = nx), in a block of their own: layer k (0: x = -2,
+// 1: x = -1, 2: x = nx, 3: x = nx+1) of row (y, z) of velocity i at
+// i*sv + xg + (z + 2) * xgz + (y + 2) * 4 + k (plane-major: right after each
+// velocity plane; velocity-major: after each velocity block's planes).
 struct Grid {
     int32_t nx, ny, nz;
     int32_t my;          // rows per plane (ny + 4)
     int64_t sy, sz, sv;  // strides of y, z and velocity (elements)
     int64_t org;         // offset of interior node (0,0,0)
-    int64_t sink;        // offset (within a velocity plane) of a region of SINK_ROWS x TILE_X elements that is never read
-    int64_t xg;          // offset (within a velocity plane) of the x-layer block, 0 if none
+    int64_t sink;        // offset from a velocity's base of a region of SINK_ROWS x TILE_X elements that is never read
+    int64_t xg;          // offset from a velocity's base of its x-layer block, 0 if none
+    int64_t xgz;         // z stride of the x-layer block
+    int64_t len;         // elements of one level (one distribution buffer)
+    int32_t plane_major; // 1: plane-major order, 0: velocity-major
 };
 
 struct FaceBC {

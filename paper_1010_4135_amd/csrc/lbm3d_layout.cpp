@@ -1,16 +1,95 @@
-// Host-side layout decisions of the lbm3d library: which kernels and tile
-// shapes take a solve, which boundary layers the kernels leave to memory.
+// Host-side layout decisions of the lbm3d library: where each node's
+// distributions sit in memory, which kernels and tile shapes take a solve,
+// which boundary layers the kernels leave to memory.
+#include "lbm3d_api_impl.h"
 #include "lbm3d_model.h"
 
 #include <algorithm>
 
 namespace lbm3d {
 
+size_t elem_size(int precision) { return precision == LBM3D_FP64 ? 8 : 4; }
+
+// Padded layout: each x row holds `ox` leading elements (the two boundary
+// layers sit just before interior x = 0, which starts on a 128-byte line),
+// the nx interior nodes and two boundary layers, rounded up to whole lines.
+Grid make_grid(const lbm3d_params* p)
+{
+    Grid g;
+    const int64_t es = (int64_t)elem_size(p->precision);
+    const int64_t line = 128 / es;
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nz = p->nz;
+    const bool dense = dense_rows(p->nx);
+    // dense rows: the interior only, rows start on a line (nx is a multiple
+    // of 64 elements); otherwise the x layers pad the rows
+    const int64_t ox = dense ? 0 : line;
+    // one cache line of padding per row, holding the two right layer nodes
+    // of the row (its first elements) and the two left layer nodes of the
+    // next row (its last elements); interior rows start on a line
+    const int64_t mxp = (p->nx + line - 1) / line * line + line;
+    const int64_t mx = dense ? p->nx : mxp;
+    const int64_t my = p->ny + 2 * NG;
+    const int64_t mz = p->nz + 2 * NG;
+    const int64_t plane = mx * my;
+    const int64_t xrows = dense ? 4 * my : 0;  // x layers of one plane's rows (dense rows)
+    const int64_t sinkn = (int64_t)SINK_ROWS * TILE_X;
+    g.my = (int32_t)my;
+    g.sy = mx;
+    // an odd number of 256-byte blocks holding at least n elements
+    const int64_t blk = 256 / es;
+    auto odd_blocks = [&](int64_t n) {
+        int64_t b = (n + blk - 1) / blk;
+        if ((b & 1) == 0) b += 1;
+        return b * blk;
+    };
+    // The sink region of the tiled step's stores from lanes outside the grid
+    // sits after one spare line past the last plane (the right layer nodes
+    // of the last row of a padded plane reach two elements past it), at the
+    // same offset from every velocity's base.
+    const bool velocity_major = (p->flags & LBM3D_VELOCITY_MAJOR) != 0;
+    if (!velocity_major) {
+        const int64_t sv = odd_blocks(plane + xrows);
+        const int64_t sz = NV * sv;
+        const int64_t sink = sz * mz + line;
+        const int64_t len = (NV - 1) * sv + sink + sinkn + line;
+        if (len * es < ((int64_t)1 << 31)) {
+            g.plane_major = 1;
+            g.sv = sv;
+            g.sz = sz;
+            g.sink = sink;
+            g.xg = dense ? plane : 0;
+            g.xgz = sz;
+            g.len = len;
+            g.org = NG * g.sz + NG * g.sy + ox;
+            return g;
+        }
+    }
+    g.plane_major = 0;
+    g.sz = plane;
+    g.sink = g.sz * mz + line;
+    const int64_t sink_end = g.sink + sinkn;
+    // dense rows: the x layers of every row (4 nodes) after the sink region
+    g.xg = dense ? sink_end + line : 0;
+    g.xgz = xrows;
+    const int64_t end = dense ? g.xg + xrows * mz : sink_end + line;
+    g.sv = odd_blocks(end);
+    g.len = NV * g.sv;
+    g.org = NG * g.sz + NG * g.sy + ox;
+    return g;
+}
+
+size_t f_bytes(const Grid& g, int precision) { return (size_t)g.len * elem_size(precision); }
+
+
 bool tiled_fits(int mode, const Grid& g)
 {
-    // the tiled kernels address a velocity plane with 32-bit byte offsets
+    // the tiled kernels reach everything from a velocity's base (its sink
+    // region included) with 32-bit byte offsets: the whole level when it is
+    // plane-major, one velocity block when it is velocity-major
     const int64_t es = mode == MODE_FP64 ? 8 : 4;
-    return g.sv * es < ((int64_t)1 << 31);
+    return (g.plane_major ? g.len : g.sv) * es < ((int64_t)1 << 31);
 }
 
 TileCfg default_tile(int mode, const Grid& g)
@@ -26,7 +105,7 @@ TileCfg default_tile(int mode, const Grid& g)
     t.by = mode == MODE_FP64 ? 4 : 8;
     t.tz = mode == MODE_FP64 ? 64 : 32;
     const int64_t es = mode == MODE_FP64 ? 8 : 4;
-    t.stream = 2 * NV * g.sv * es > STREAM_MIN_BYTES;
+    t.stream = 2 * g.len * es > STREAM_MIN_BYTES;
     if (g.nz < 2 * t.tz) t.tz = std::max(2, g.nz / 4);
     return t;
 }

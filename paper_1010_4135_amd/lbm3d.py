@@ -20,7 +20,7 @@ OK, E_INVAL, E_UNSTABLE, E_NOMEM, E_DEVICE, E_STATE, E_NONFINITE, E_NOTFOUND, E_
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, FP32, FP32_T64 = 0, 1, 2
 PERIODIC, OUTFLOW, INFLOW, REFLECT = 0, 1, 2, 3
-NO_DISSIPATION, UPWIND2, CHECK_STABILITY = 1, 2, 4
+NO_DISSIPATION, UPWIND2, CHECK_STABILITY, VELOCITY_MAJOR = 1, 2, 4, 8
 HEALTH_NONFINITE, HEALTH_RHO_NONPOS, HEALTH_T_NONPOS = 1, 2, 4
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_t64": FP32_T64}
 NV = 15

@@ -73,7 +73,7 @@ def test_footprint_counts_both_buffers():
     (dict(bc=(7, 7, 0, 0, 0, 0)), -1),
     (dict(grid=(1, 4, 4), bc=(1, 1, 0, 0, 0, 0)), -1),  # extrapolation needs 2 nodes
     (dict(precision=5), -1),
-    (dict(flags=8), -1),
+    (dict(flags=16), -1),
     (dict(bc=(2, 1, 0, 0, 0, 0)), -1),       # inflow state with rho = 0
     (dict(dt=1e-2), -2),                     # Courant number above 1
     (dict(dt=1e-5, tau=1e-6), -2),           # dt/tau above 2
