@@ -34,7 +34,8 @@ Beside it:
                 results' error against it);
   serving       an open Poisson stream of 200 mixed solves through the
                 continuous-batching server vs the plain one-at-a-time FP64
-                loop: capacities and their ratio, and at 50%, 80% and 95% of
+                loop: capacities and their ratio (also against the same
+                loop in the served precision), and at 50%, 80% and 95% of
                 the served capacity solves/s, p50/p99 time to solution
                 (overall and per grid size), the server's tick counters and
                 the served results' error against FP64 (top-level figures:
@@ -288,6 +289,8 @@ def serve_bench(lbm3d, inputs, metrics, seed: int, count: int = 200):
     - baseline: the plain one-at-a-time FP64 loop over the same requests
       back to back (create, init, step, read back, free), which gives each
       request's service time, the FP64 results and the baseline capacity;
+      the same loop in the served precision gives the capacity ratio at
+      equal precision;
     - at 50%, 80% and 95% of the served capacity: the served path on the
       open stream, measured; the baseline's latencies are its measured
       service times replayed through the FIFO queue of the same arrival
@@ -326,6 +329,15 @@ def serve_bench(lbm3d, inputs, metrics, seed: int, count: int = 200):
             base.append(s.moments())
         service.append(time.perf_counter() - t0)
     base_capacity = count / sum(service)
+    # the same loop in the served precision, to separate what serving gains
+    # from what FP32 storage gains
+    t0 = time.perf_counter()
+    for _, c in base_trace:
+        with lbm3d.Solver(dict(c.params, precision="fp32_t64")) as s:
+            s.init(*c.fields)
+            s.step(c.steps)
+            s.moments()
+    same_capacity = count / (time.perf_counter() - t0)
     _, _, w_cap, st_cap = served(1e12)
     capacity = count / w_cap
     out = {"requests": count, "served_precision": "fp32_t64",
@@ -334,6 +346,8 @@ def serve_bench(lbm3d, inputs, metrics, seed: int, count: int = 200):
            "served_capacity_solves_per_s": round(capacity, 3),
            "baseline_capacity_solves_per_s": round(base_capacity, 3),
            "capacity_ratio": round(capacity / base_capacity, 3),
+           "same_precision_loop_capacity_solves_per_s": round(same_capacity, 3),
+           "capacity_ratio_same_precision": round(capacity / same_capacity, 3),
            "capacity_run_busy_frac": round(st_cap["busy_s"] / max(w_cap, 1e-9), 3)}
     grids = sorted({c.grid for _, c in base_trace})
     levels = []
