@@ -122,3 +122,29 @@ def test_checkpoint_moves_between_plane_orders():
     assert np.array_equal(a.get_f(), b.get_f())
     a.close()
     b.close()
+
+
+def test_level_above_2gib_stays_velocity_major_and_matches_oracle():
+    """An FP64 level of 256x256x282 nodes would take 2.33 GB plane-major,
+    beyond the 32-bit byte offsets the tiled kernels reach from a velocity's
+    base, so it is stored velocity-major (155 MB per velocity block) and
+    still runs tiled: 3 steps against the FP64 oracle at the FP64 bar."""
+    import os
+
+    import oracle
+    from paper_1010_4135_amd import metrics
+
+    case = inputs.riemann_3d(12, grid=(256, 256, 282), precision="fp64")
+    print("[layout] 256x256x282 fp64, 3 steps", flush=True)
+    s = _run(case.params, case.fields, 3)
+    by, tz = s.get_tile()
+    assert by > 0, "the velocity-major level runs tiled"
+    mg = s.moments()
+    s.close()
+    oracle.set_threads(len(os.sched_getaffinity(0)))
+    o = oracle.Oracle(case.params)
+    o.init(*case.fields)
+    o.step(3)
+    err = metrics.rel_l1(mg, o.moments())
+    print("[layout] 256x256x282 fp64 vs oracle " + " ".join(f"{k}={v:.3e}" for k, v in err.items()), flush=True)
+    assert max(err.values()) <= 1e-12, err
