@@ -6,6 +6,7 @@
 // analysis and admission, the batched step's work plans, the autotuner's
 // cache files, and the error paths of create / server without a device.
 #include "../../include/lbm3d.h"
+#include "../../paper_1010_4135_amd/csrc/lbm3d_api_impl.h"
 #include "../../paper_1010_4135_amd/csrc/lbm3d_internal.h"
 
 #include <cmath>
@@ -59,6 +60,68 @@ static lbm3d_params base(int nx, int ny, int nz, int prec)
     return p;
 }
 
+// The memory layout of a level (make_grid), for small random grids in both
+// plane orders and every precision: each node the kernels address (interior
+// and the two layers per face; with dense rows the x layers sit in the
+// x-layer block instead), every velocity's sink region and x-layer block lie
+// inside the level; no two of them share an element, except that the sink
+// regions of different velocities may overlap one another (their contents
+// are never read).
+static void check_layouts(std::mt19937& rng)
+{
+    for (int k = 0; k < 240; k++) {
+        const int prec = (int)(rng() % 3);
+        lbm3d_params p = base(1 + (int)(rng() % 100), 1 + (int)(rng() % 20), 1 + (int)(rng() % 12), prec);
+        if (k % 3 == 0) p.nx = 64 * (1 + (int)(rng() % 2));  // dense rows
+        const bool vm = rng() % 2;
+        if (vm) p.flags = LBM3D_VELOCITY_MAJOR;
+        const lbm3d::Grid g = lbm3d::make_grid(&p);
+        const int64_t es = prec == LBM3D_FP64 ? 8 : 4;
+        const bool dense = lbm3d::dense_rows(p.nx);
+        EXPECT(g.plane_major == (vm ? 0 : 1));
+        EXPECT((int64_t)lbm3d::f_bytes(g, prec) == g.len * es);
+        EXPECT(lbm3d::tiled_fits(prec, g));
+        EXPECT(g.sv % (256 / es) == 0 && (g.sv / (256 / es)) % 2 == 1);
+        std::vector<int32_t> own((size_t)g.len, 0);
+        int32_t id = 0;
+        bool ok = true;
+        auto claim = [&](int64_t a) {
+            ++id;
+            if (a < 0 || a >= g.len || own[(size_t)a] != 0) {
+                ok = false;
+                return;
+            }
+            own[(size_t)a] = id;
+        };
+        const int x0 = dense ? 0 : -2, x1 = dense ? p.nx : p.nx + 2;
+        for (int i = 0; i < 15; i++)
+            for (int z = -2; z < p.nz + 2; z++)
+                for (int y = -2; y < p.ny + 2; y++)
+                    for (int x = x0; x < x1; x++) claim(i * g.sv + g.org + z * g.sz + y * g.sy + x);
+        if (dense) {
+            EXPECT(g.xg != 0);
+            for (int i = 0; i < 15; i++)
+                for (int z = 0; z < p.nz; z++)
+                    for (int y = 0; y < p.ny; y++)
+                        for (int c = 0; c < 4; c++) claim(i * g.sv + g.xg + (z + 2) * g.xgz + (y + 2) * 4 + c);
+        } else {
+            EXPECT(g.xg == 0);
+        }
+        EXPECT(ok);
+        // the tiled kernels' clamped loads (x up to nx + 1 with dense rows)
+        // stay inside the level
+        if (dense) EXPECT(14 * g.sv + g.org + (p.nz + 1) * g.sz + (p.ny + 1) * g.sy + p.nx + 1 < g.len);
+        for (int i = 0; i < 15; i++)
+            for (int64_t e = 0; e < (int64_t)lbm3d::SINK_ROWS * lbm3d::TILE_X; e++) {
+                const int64_t a = i * g.sv + g.sink + e;
+                if (a < 0 || a >= g.len || own[(size_t)a] > 0) ok = false;
+            }
+        EXPECT(ok);
+        // every sink element lies past every plane the step writes
+        EXPECT(g.sink - g.org - (int64_t)(p.nz - 1) * g.sz >= 0);
+    }
+}
+
 int main(int argc, char** argv)
 {
     const std::string tmp = argc > 1 ? argv[1] : "/tmp";
@@ -77,6 +140,7 @@ int main(int argc, char** argv)
         EXPECT(rc == LBM3D_OK || rc == LBM3D_E_INVAL || rc == LBM3D_E_UNSTABLE);
         if (rc == LBM3D_OK) EXPECT(bytes >= (size_t)2 * 15 * p.nx * p.ny * p.nz * (p.precision == 0 ? 8 : 4));
     }
+    check_layouts(rng);
     // stability analysis and admission
     for (int k = 0; k < 20; k++) {
         lbm3d_params p = base(6, 5, 4, 0);
