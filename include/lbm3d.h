@@ -297,22 +297,24 @@ int32_t lbm3d_set_f(lbm3d_t h, const void* host, size_t bytes);
 
 /* Advance `count` independent solves (any mix of sizes, all of the same
  * precision) by nsteps[k] steps each: the time step of Sec. 3, Eqs. (nnd),
- * (lp), (fi1), applied to every member.  Each step of the group is one
- * launch of a persistent kernel whose workgroups take 64 x BY x TZ tiles of
- * every solve that still has steps to do from per-XCD work lists (see
- * lbm3d_batch_plan); groups of steps are replayed from captured HIP graphs.
- * Results are bitwise identical to stepping each solve alone.  Blocking.
- * E_INVAL for mixed precisions, duplicate or NULL handles, count < 1, a
- * negative step count, or a solve whose velocity plane (about nx*ny*nz
- * elements) reaches 2 GiB: the batched kernel addresses a plane with 32-bit
- * offsets.  E_STATE if a member is not initialised. */
+ * (lp), (fi1), applied to every member.  The group runs max(nsteps) steps,
+ * each one launch of a persistent kernel whose workgroups take 64 x BY x TZ
+ * tiles from per-XCD work lists (see lbm3d_batch_plan); a member takes part
+ * while it has steps to do (a device-side count per member, advanced by a
+ * small launch after each step), and runs of 16 steps are replayed from a
+ * captured HIP graph.  Results are bitwise identical to stepping each solve
+ * alone.  Blocking.  E_INVAL for mixed precisions, duplicate or NULL
+ * handles, count < 1, a negative step count, a solve with the
+ * second-order upwind flag, or one beyond the tiled kernels' 32-bit
+ * offsets (a velocity-major level whose velocity block reaches 2 GiB).
+ * E_STATE if a member is not initialised. */
 int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* nsteps);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * step as lbm3d_batch_step, with the same arguments, errors and results
  * (bitwise), that allocates nothing.  Its work tables (the solve table,
- * tile lists, counters, boundary-layer jobs and health words) go into a
+ * tile lists, counters, boundary-layer jobs, step counts and health words) go into a
  * static device array of 4 MiB per device, held until the process ends,
  * instead of a hipMalloc'd buffer; they are copied there from host memory
  * with hipMemcpyAsync on the first member's stream, and every step is
@@ -368,14 +370,16 @@ typedef struct {
     uint32_t health;                  /* LBM3D_HEALTH_* of the solve */
 } lbm3d_timing;
 
-/* A server owns one worker thread that admits submitted solves while their
+/* A server owns a worker thread that admits submitted solves while their
  * device footprint fits in hbm_budget_bytes and fewer than max_active are
  * running, keeps their state resident on the device, advances all active
  * solves together in batched ticks (continuous batching: solves admitted
- * between ticks join the next one), and completes a ticket when its solve
- * has done its steps, or early, with E_NONFINITE, after the first tick that
- * leaves it non-finite.  Solves of any precision may be mixed; each tick
- * groups them by precision. */
+ * between ticks join the next one; within a tick each solve takes only the
+ * steps it still needs), and completes a ticket when its solve has done its
+ * steps, or early, with E_NONFINITE, after the first tick that leaves it
+ * non-finite.  A second thread creates and initialises admitted solves and
+ * reads back finished ones while the ticks run.  Solves of any precision
+ * may be mixed; each tick groups them by precision. */
 int32_t lbm3d_server_create(size_t hbm_budget_bytes, int32_t max_active, lbm3d_server_t* out);
 
 /* Steps per batched tick (default 32): solves submitted during a tick join

@@ -191,7 +191,8 @@ static size_t tables_need(size_t nmembers, size_t ntiles, size_t nljobs, size_t 
 {
     return align256(nmembers * sizeof(BatchSolve)) + align256(ntiles * sizeof(BatchTile)) +
            align256(sizeof(BatchQueue)) + align256(nljobs * sizeof(BatchLayerJob)) +
-           align256(nlblocks * sizeof(int32_t)) + nmembers * sizeof(uint32_t) + 256;
+           align256(nlblocks * sizeof(int32_t)) + align256(nmembers * sizeof(BatchCount)) +
+           nmembers * sizeof(uint32_t) + 256;
 }
 
 size_t BatchPlan::table_bytes(const std::vector<lbm3d_solver*>& members, int tz)
@@ -219,7 +220,8 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     release_graph();
     members_ = members;
     plan_ = TilePlan();
-    parity_ = 0;
+    hcount_.assign(members.size(), BatchCount{0, 0});
+    count_pending_ = false;
     if (members.empty()) return LBM3D_OK;
     mode_ = members[0]->mode;
     by_ = mode_ == LBM3D_FP64 ? 4 : 8;
@@ -284,12 +286,15 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     dqueue_ = (BatchQueue*)((char*)dtiles_ + align256(tb));
     dlayers_ = (BatchLayerJob*)((char*)dqueue_ + align256(sizeof(BatchQueue)));
     dblockjob_ = (int32_t*)((char*)dlayers_ + align256(lb));
-    dhealth_ = (uint32_t*)((char*)dblockjob_ + align256(bb));
+    const size_t cb = hcount_.size() * sizeof(BatchCount);
+    dcount_ = (BatchCount*)((char*)dblockjob_ + align256(bb));
+    dhealth_ = (uint32_t*)((char*)dcount_ + align256(cb));
     hipError_t e = hipMemcpyAsync(dsolves_, table.data(), sb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dtiles_, plan_.tiles.data(), tb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dqueue_, &plan_.queue, sizeof(BatchQueue), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && lb) e = hipMemcpyAsync(dlayers_, ljobs.data(), lb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && bb) e = hipMemcpyAsync(dblockjob_, block_job.data(), bb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dcount_, hcount_.data(), cb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables die at return
     last_stream_ = nullptr;
     return herr(e);
@@ -303,6 +308,7 @@ int32_t BatchPlan::health(std::vector<uint32_t>& out, hipStream_t s)
     if (e == hipSuccess)
         e = hipMemcpyAsync(out.data(), dhealth_, out.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && s == last_stream_) count_pending_ = false;
     return herr(e);
 }
 
@@ -315,34 +321,60 @@ hipError_t BatchPlan::launch_at(int parity, hipStream_t s)
 hipError_t BatchPlan::enqueue(int parity, hipStream_t s)
 {
     hipError_t e = launch_batch_step(mode_, by_, stream_, dsolves_, dtiles_, dqueue_, plan_.nlists, plan_.nblocks,
-                                     parity, s);
+                                     parity, dcount_, s);
     if (e != hipSuccess) return e;
     // boundary layers the tiles do not form themselves, all members at once
-    return launch_batch_layers(mode_, dsolves_, dlayers_, dblockjob_, nlblocks_, parity, s);
+    e = launch_batch_layers(mode_, dsolves_, dlayers_, dblockjob_, nlblocks_, parity, dcount_, s);
+    if (e != hipSuccess || parity >= 0) return e;
+    return launch_batch_count(dcount_, (int)members_.size(), s);
 }
 
-int32_t BatchPlan::run(int64_t k, hipStream_t s, bool graphs)
+int32_t BatchPlan::run(int64_t k, hipStream_t s, bool graphs, const std::vector<int64_t>* limit)
 {
     if (members_.empty() || k <= 0) return LBM3D_OK;
-    last_stream_ = s;
-    int64_t left = k;
-    // align to an even parity so the captured graph (parities 0,1,...) applies
-    if (graphs && (parity_ & 1)) {
-        hipError_t e = enqueue(1, s);
-        if (e != hipSuccess) return herr(e);
-        parity_ ^= 1;
-        left--;
+    if (limit && limit->size() != members_.size()) return LBM3D_E_INVAL;
+    // the counts are 32-bit: very long runs go in pieces
+    constexpr int64_t PIECE = (int64_t)1 << 30;
+    if (k > PIECE) {
+        std::vector<int64_t> rest = limit ? *limit : std::vector<int64_t>(members_.size(), k);
+        for (int64_t left = k; left > 0;) {
+            const int64_t c = std::min(left, PIECE);
+            int32_t rc = run(c, s, graphs, &rest);
+            if (rc) return rc;
+            for (int64_t& r : rest) r = std::max<int64_t>(0, r - c);
+            left -= c;
+        }
+        return LBM3D_OK;
     }
+    // the counts of the last run may still be on their way from hcount_
+    if (count_pending_ && last_stream_ && hipStreamSynchronize(last_stream_) != hipSuccess) return LBM3D_E_DEVICE;
+    count_pending_ = false;
+    last_stream_ = s;
+    // this run's counts: done restarts at each member's parity since build
+    // (so it never grows), target = done + the member's steps
+    std::vector<int64_t> steps(members_.size(), k);
+    for (size_t m = 0; m < members_.size(); m++) {
+        if (limit) steps[m] = std::max<int64_t>(0, std::min<int64_t>(k, (*limit)[m]));
+        hcount_[m].done &= 1;
+        hcount_[m].target = hcount_[m].done + (int32_t)steps[m];
+    }
+    hipError_t e = hipMemcpyAsync(dcount_, hcount_.data(), hcount_.size() * sizeof(BatchCount),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return herr(e);
+    count_pending_ = true;
+    int64_t left = k;
+    // the launches carry nothing step-specific (each member's parity comes
+    // from its count), so one captured run of BATCH_GRAPH_STEPS serves all
     while (graphs && left >= BATCH_GRAPH_STEPS) {
         if (!graph_) {
             if (!capture_stream_) {
-                hipError_t e = hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking);
+                e = hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking);
                 if (e != hipSuccess) return herr(e);
             }
             hipGraph_t graph = nullptr;
-            hipError_t e = hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal);
+            e = hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return herr(e);
-            for (int j = 0; j < BATCH_GRAPH_STEPS && e == hipSuccess; j++) e = enqueue(j & 1, capture_stream_);
+            for (int j = 0; j < BATCH_GRAPH_STEPS && e == hipSuccess; j++) e = enqueue(-1, capture_stream_);
             hipError_t e2 = hipStreamEndCapture(capture_stream_, &graph);
             if (e != hipSuccess || e2 != hipSuccess) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -352,24 +384,28 @@ int32_t BatchPlan::run(int64_t k, hipStream_t s, bool graphs)
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) return herr(e);
         }
-        hipError_t e = hipGraphLaunch(graph_, s);
+        e = hipGraphLaunch(graph_, s);
         if (e != hipSuccess) return herr(e);
         left -= BATCH_GRAPH_STEPS;
     }
     for (; left > 0; left--) {
-        hipError_t e = enqueue(parity_, s);
+        e = enqueue(-1, s);
         if (e != hipSuccess) return herr(e);
-        parity_ ^= 1;
     }
-    // members advance by k steps; their current buffer flips with odd k (the
-    // device table keeps the build-time buffers and parity_ the offset)
-    for (lbm3d_solver* h : members_) {
-        h->steps += k;
-        if (k & 1) h->cur ^= 1;
+    // members advance by their steps; their current buffer flips with an
+    // odd count (the device table keeps the build-time buffers, and each
+    // count's done its parity since build)
+    for (size_t m = 0; m < members_.size(); m++) {
+        lbm3d_solver* h = members_[m];
+        const int64_t n = steps[m];
+        hcount_[m].done = (hcount_[m].done + (int32_t)(n & 1)) & 1;
+        if (n == 0) continue;
+        h->steps += n;
+        if (n & 1) h->cur ^= 1;
         // a member that steps alone untiled reads every layer from memory:
         // refresh the ones the tiled batch kernel formed itself
         if (h->tile.by == 0) {
-            hipError_t e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[h->cur], s);
+            e = launch_ghosts(h->mode, h->g, h->bc, h->md, h->p.inflow, false, h->f[h->cur], s);
             if (e != hipSuccess) return herr(e);
         }
     }
@@ -397,22 +433,20 @@ int32_t check_batch(lbm3d_t* hs, int32_t count)
 int32_t batch_advance(lbm3d_t* hs, int32_t count, const int64_t* nsteps, hipStream_t s, BatchPlan& plan,
                       void* dev, size_t cap, bool graphs)
 {
-    std::vector<int64_t> left(nsteps, nsteps + count);
-    for (;;) {
-        std::vector<lbm3d_solver*> active;
-        int64_t k = 0;
-        for (int32_t j = 0; j < count; j++)
-            if (left[j] > 0) {
-                active.push_back(hs[j]);
-                k = (k == 0) ? left[j] : std::min(k, left[j]);
-            }
-        if (active.empty()) break;
+    std::vector<lbm3d_solver*> active;
+    std::vector<int64_t> limit;
+    int64_t k = 0;
+    for (int32_t j = 0; j < count; j++)
+        if (nsteps[j] > 0) {
+            active.push_back(hs[j]);
+            limit.push_back(nsteps[j]);
+            k = std::max(k, nsteps[j]);
+        }
+    if (!active.empty()) {
         int32_t rc = plan.build(active, s, 0, dev, cap);
         if (rc) return rc;
-        rc = plan.run(k, s, graphs);
+        rc = plan.run(k, s, graphs, &limit);
         if (rc) return rc;
-        for (int32_t j = 0; j < count; j++)
-            if (left[j] > 0) left[j] -= k;
     }
     return hipStreamSynchronize(s) == hipSuccess ? LBM3D_OK : LBM3D_E_DEVICE;
 }

@@ -49,10 +49,12 @@ public:
     // (relative to build) into the other one, boundary layers included,
     // without advancing the members' step counters or parity (for timing).
     hipError_t launch_at(int parity, hipStream_t s);
-    // Enqueue k steps of every member on `s` and update the members'
-    // buffer parity and step counters; `graphs` = false launches every step
+    // Enqueue k launches of the step on `s`, in which member m takes
+    // min(k, limit[m]) steps (k each without `limit`; a member that is done
+    // sits out the remaining launches), and update the members' buffer
+    // parity and step counters; `graphs` = false launches every step
     // directly (no graph is instantiated).
-    int32_t run(int64_t k, hipStream_t s, bool graphs = true);
+    int32_t run(int64_t k, hipStream_t s, bool graphs = true, const std::vector<int64_t>* limit = nullptr);
     // Health words of the members (in build order) after the work queued
     // on `s`; waits for `s`.
     int32_t health(std::vector<uint32_t>& out, hipStream_t s);
@@ -61,7 +63,7 @@ public:
     int tz() const { return tz_; }
 
 private:
-    hipError_t enqueue(int parity, hipStream_t s);
+    hipError_t enqueue(int parity, hipStream_t s);  // parity < 0: by the members' counts
     void release_graph();
 
     std::vector<lbm3d_solver*> members_;
@@ -76,18 +78,20 @@ private:
     BatchLayerJob* dlayers_ = nullptr;  // boundary-layer jobs (sorted by first workgroup)
     int32_t* dblockjob_ = nullptr;      // job of each boundary-layer workgroup
     uint32_t* dhealth_ = nullptr;       // gathered health words, one per member
+    BatchCount* dcount_ = nullptr;      // step counts of the members in the current run
+    std::vector<BatchCount> hcount_;    // their host copy (source of the upload; done = parity since build)
+    bool count_pending_ = false;        // hcount_ was uploaded and the stream not waited for since
     int nljobs_ = 0, nlblocks_ = 0;
     std::vector<uint32_t> ghost_rest_;  // per member: faces left to the boundary-layer launch
     hipGraphExec_t graph_ = nullptr;
     hipStream_t capture_stream_ = nullptr;
     hipStream_t last_stream_ = nullptr;  // stream of the last enqueued work (drained before teardown)
-    int parity_ = 0;  // parity of the next step relative to build()
 };
 
 // Checks shared by the batched entry points (E_INVAL / E_STATE).
 int32_t check_batch(lbm3d_t* hs, int32_t count);
-// Advance members by their own step counts (runs of the common count with
-// the members that still have steps to do), then wait for `s`.  Tables go
+// Advance members by their own step counts (one run of the largest count,
+// the others sitting out its last launches), then wait for `s`.  Tables go
 // into `dev` (cap bytes) when given; `graphs` = false launches every step
 // directly.
 int32_t batch_advance(lbm3d_t* hs, int32_t count, const int64_t* nsteps, hipStream_t s, BatchPlan& plan,

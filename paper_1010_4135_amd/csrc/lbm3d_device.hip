@@ -147,7 +147,7 @@ __device__ __forceinline__ void keep_model(Model<T>& m)
 template <int MODE, int BY, bool NT>
 __global__ void __launch_bounds__(TILE_X * BY)
 k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict__ tiles, BatchQueue* queue,
-             int nlists, int parity)
+             int nlists, int parity, const BatchCount* __restrict__ counts)
 {
     using S = typename Types<MODE>::S;
     __shared__ TilePlane<BY, S> P[2];
@@ -173,26 +173,47 @@ k_batch_step(const BatchSolve* __restrict__ solves, const BatchTile* __restrict_
         if (k >= cnt) break;
         const BatchTile tile = tiles[first + k];
         const BatchSolve& d = solves[tile.solve];
-        StepArgs<MODE> A;
-        A.g = d.g;
-        A.bc = d.bc;
-        const int cur = d.cur0 ^ parity;
-        A.f = (const S*)d.f[cur];
-        A.fn = (S*)d.f[cur ^ 1];
-        A.health = d.health;
+        // the member's parity: given (timing trials), or from its own step
+        // count, which also says whether it still steps in this run (the
+        // same for the whole workgroup, so the barriers stay uniform)
+        int par = parity;
+        bool run = true;
+        if (parity < 0) {
+            const BatchCount c = counts[tile.solve];
+            par = c.done & 1;
+            run = c.done < c.target;
+        }
+        if (run) {
+            StepArgs<MODE> A;
+            A.g = d.g;
+            A.bc = d.bc;
+            const int cur = d.cur0 ^ par;
+            A.f = (const S*)d.f[cur];
+            A.fn = (S*)d.f[cur ^ 1];
+            A.health = d.health;
 #pragma unroll
-        for (int j = 0; j < 10; j++) A.xin[j / 5][j % 5] = d.xin[j / 5][j % 5];
-        Model<double> md = d.md;
-        Model<float> mf = d.mf;
-        // the tile's solve is read once per tile: without this the compiler
-        // re-loads its constants and strides from the table in every plane,
-        // each a scalar-memory round trip the plane then waits for
-        keep(A.g.sy); keep(A.g.sz); keep(A.g.sv); keep(A.g.org); keep(A.g.sink); keep(A.g.xg);
-        keep(A.f); keep(A.fn);
-        keep_model(mf);
-        step_tile<MODE, BY, true, NT>(A, md, mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
+            for (int j = 0; j < 10; j++) A.xin[j / 5][j % 5] = d.xin[j / 5][j % 5];
+            Model<double> md = d.md;
+            Model<float> mf = d.mf;
+            // the tile's solve is read once per tile: without this the
+            // compiler re-loads its constants and strides from the table in
+            // every plane, each a scalar-memory round trip the plane then
+            // waits for
+            keep(A.g.sy); keep(A.g.sz); keep(A.g.sv); keep(A.g.org); keep(A.g.sink); keep(A.g.xg);
+            keep(A.f); keep(A.fn);
+            keep_model(mf);
+            step_tile<MODE, BY, true, NT>(A, md, mf, tile.txi * TILE_X, tile.tyi * BY, tile.z0, tile.z1, P);
+        }
         lds_barrier();  // the plane buffers (and s_k) are reused by the next tile
     }
+}
+
+// Step counts of the batch members after a step: done += 1 while below the
+// target.
+__global__ void __launch_bounds__(64) k_batch_count(BatchCount* __restrict__ counts, int n)
+{
+    const int m = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (m < n && counts[m].done < counts[m].target) counts[m].done += 1;
 }
 
 // Health words of the members of a batch, gathered into one array.
@@ -316,16 +337,24 @@ k_layers(StepArgs<MODE> A, Model<double> md, Model<float> mf, FixedStates fx, ui
 template <int MODE>
 __global__ void __launch_bounds__(64)
 k_layers_batch(const BatchSolve* __restrict__ solves, const BatchLayerJob* __restrict__ jobs,
-               const int32_t* __restrict__ block_job, int parity)
+               const int32_t* __restrict__ block_job, int parity, const BatchCount* __restrict__ counts)
 {
     using S = typename Types<MODE>::S;
     const int b = (int)blockIdx.x;
     const BatchLayerJob jb = jobs[block_job[b]];
     const BatchSolve& d = solves[jb.solve];
+    int par = parity;
+    if (parity < 0) {
+        // (read before this step's count; members past their target did
+        // not step)
+        const BatchCount c = counts[jb.solve];
+        if (c.done >= c.target) return;
+        par = c.done & 1;
+    }
     StepArgs<MODE> A;
     A.g = d.g;
     A.bc = d.bc;
-    const int cur = d.cur0 ^ parity;
+    const int cur = d.cur0 ^ par;
     A.f = nullptr;
     A.fn = (S*)d.f[cur ^ 1];
     A.health = nullptr;
@@ -598,33 +627,47 @@ hipError_t launch_gather_health(const BatchSolve* solves, int n, uint32_t* out, 
 }
 
 hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLayerJob* jobs, const int32_t* block_job,
-                               int nblocks, int parity, hipStream_t s)
+                               int nblocks, int parity, const BatchCount* counts, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    LBM3D_DISPATCH(mode, k_layers_batch<MD><<<dim3(nblocks), dim3(64), 0, s>>>(solves, jobs, block_job, parity));
+    if (parity < 0 && !counts) return hipErrorInvalidValue;
+    LBM3D_DISPATCH(mode,
+                   k_layers_batch<MD><<<dim3(nblocks), dim3(64), 0, s>>>(solves, jobs, block_job, parity, counts));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_count(BatchCount* counts, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_batch_count<<<dim3(blocks_for(n, 64)), dim3(64), 0, s>>>(counts, n);
     return hipGetLastError();
 }
 
 template <int MODE, int BY>
 static void launch_batch(unsigned nblocks, bool stream, const BatchSolve* solves, const BatchTile* tiles,
-                         BatchQueue* queue, int nlists, int parity, hipStream_t s)
+                         BatchQueue* queue, int nlists, int parity, const BatchCount* counts, hipStream_t s)
 {
     if (stream)
-        k_batch_step<MODE, BY, true><<<dim3(nblocks), dim3(TILE_X * BY), 0, s>>>(solves, tiles, queue, nlists, parity);
+        k_batch_step<MODE, BY, true>
+            <<<dim3(nblocks), dim3(TILE_X * BY), 0, s>>>(solves, tiles, queue, nlists, parity, counts);
     else
-        k_batch_step<MODE, BY, false><<<dim3(nblocks), dim3(TILE_X * BY), 0, s>>>(solves, tiles, queue, nlists, parity);
+        k_batch_step<MODE, BY, false>
+            <<<dim3(nblocks), dim3(TILE_X * BY), 0, s>>>(solves, tiles, queue, nlists, parity, counts);
 }
 
 hipError_t launch_batch_step(int mode, int by, bool stream, const BatchSolve* solves, const BatchTile* tiles,
-                             BatchQueue* queue, int nlists, int nblocks, int parity, hipStream_t s)
+                             BatchQueue* queue, int nlists, int nblocks, int parity, const BatchCount* counts,
+                             hipStream_t s)
 {
     if (nblocks <= 0 || nlists <= 0 || nlists > BATCH_MAX_LISTS || nblocks % nlists) return hipErrorInvalidValue;
+    if (parity < 0 && !counts) return hipErrorInvalidValue;
     // the batch's tile heights: 4 rows in FP64, 8 in the FP32 modes
     if (by != (mode == MODE_FP64 ? 4 : 8)) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)nblocks;
-    if (mode == MODE_FP64) launch_batch<MODE_FP64, 4>(nb, stream, solves, tiles, queue, nlists, parity, s);
-    else if (mode == MODE_FP32) launch_batch<MODE_FP32, 8>(nb, stream, solves, tiles, queue, nlists, parity, s);
-    else launch_batch<MODE_FP32_T64, 8>(nb, stream, solves, tiles, queue, nlists, parity, s);
+    if (mode == MODE_FP64) launch_batch<MODE_FP64, 4>(nb, stream, solves, tiles, queue, nlists, parity, counts, s);
+    else if (mode == MODE_FP32)
+        launch_batch<MODE_FP32, 8>(nb, stream, solves, tiles, queue, nlists, parity, counts, s);
+    else launch_batch<MODE_FP32_T64, 8>(nb, stream, solves, tiles, queue, nlists, parity, counts, s);
     return hipGetLastError();
 }
 

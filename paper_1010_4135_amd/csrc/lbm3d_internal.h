@@ -101,6 +101,14 @@ struct BatchSolve {
 
 // One solve's share of the batched boundary-layer launch: workgroups
 // [first, next job's first) of 64 lines each over the faces in `faces`.
+// Step count of a batch member within a run of the batched step: it takes
+// part in the launches while done < target, and its current buffer is
+// cur0 ^ (done & 1).  A counting launch after each step advances done.
+struct BatchCount {
+    int32_t done;
+    int32_t target;
+};
+
 struct BatchLayerJob {
     int32_t solve;
     uint32_t faces;
@@ -154,15 +162,21 @@ hipError_t launch_pack(int mode, const Grid& g, const void* f, void* dense, bool
 // One step of every solve in `solves` (device table) over the packed tile
 // list (device); `parity` selects f[cur0 ^ parity] as the current level.
 // Boundary layers of the members of a batch after a step (one launch).
+// parity >= 0: every member steps from its buffer of that parity (relative
+// to build); parity < 0: each member steps per its BatchCount (see above).
 hipError_t launch_batch_layers(int mode, const BatchSolve* solves, const BatchLayerJob* jobs, const int32_t* block_job,
-                               int nblocks, int parity, hipStream_t s);
+                               int nblocks, int parity, const BatchCount* counts, hipStream_t s);
+// done += 1 for each of the n members with done < target.
+hipError_t launch_batch_count(BatchCount* counts, int n, hipStream_t s);
 // out[k] = the health word of member k (n members).
 hipError_t launch_gather_health(const BatchSolve* solves, int n, uint32_t* out, hipStream_t s);
-// One step of every member: `nblocks` persistent workgroups (a multiple of
-// `nlists`); workgroup b works on list b mod nlists.  `stream`: the store
-// kind of the new level (see STREAM_MIN_BYTES).
+// One step of every member (parity as for launch_batch_layers): `nblocks`
+// persistent workgroups (a multiple of `nlists`); workgroup b works on list
+// b mod nlists.  `stream`: the store kind of the new level (see
+// STREAM_MIN_BYTES).
 hipError_t launch_batch_step(int mode, int by, bool stream, const BatchSolve* solves, const BatchTile* tiles,
-                             BatchQueue* queue, int nlists, int nblocks, int parity, hipStream_t s);
+                             BatchQueue* queue, int nlists, int nblocks, int parity, const BatchCount* counts,
+                             hipStream_t s);
 
 // block shape of the untiled step kernel; x extent of a tile of the tiled one;
 // block size of the conservation reduction

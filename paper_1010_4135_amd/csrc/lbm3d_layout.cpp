@@ -123,7 +123,7 @@ uint32_t ghost_faces(const Grid& g, const FaceBC& bc, bool tiled)
 {
     uint32_t m = 0;
     for (int face = 0; face < 6; face++) {
-        const int kind = bc.kind[face], axis = face >> 1;
+        const int kind = bc.kind[face];
         if (kind == BC_INFLOW) continue;
         // the tiles form the -x layers, and the +x layers unless the last
         // tile holds a single column (see x_forms)

@@ -2,7 +2,9 @@
 // their device footprint fits the budget and a slot is free, keeps their
 // state resident on the device, advances all active solves together in
 // batched ticks (one persistent launch per step per precision group), and
-// completes each ticket when its solve has done its steps.
+// completes each ticket when its solve has done its steps.  A helper thread
+// does the host work of admitting (create, upload, initialise) and of
+// completing (read back) while the ticks run.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -19,6 +21,9 @@
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// ticks a membership must last before its steps are captured as a graph
+constexpr int64_t GRAPH_AFTER_TICKS = 8;
 
 struct Ticket {
     uint64_t id = 0;
@@ -45,7 +50,7 @@ struct lbm3d_server {
     int device = 0;
     Clock::time_point t0;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_help;
     std::deque<Ticket*> queue;
     std::vector<Ticket*> active;
     std::unordered_map<uint64_t, std::unique_ptr<Ticket>> tickets;
@@ -54,20 +59,54 @@ struct lbm3d_server {
     bool stop = false;
     bool membership_changed = true;
     std::thread worker;
+    // The helper thread creates and initialises admitted solves and reads
+    // back finished ones (on the side stream), so that the worker, which
+    // runs the ticks, never holds up the next tick with that host work.
+    struct Task {
+        Ticket* t;
+        int32_t status;
+        bool admit;  // admit (create and initialise) or finish (read back)
+    };
+    std::thread helper;
+    std::deque<Task> tasks;       // for the helper, in order
+    int helping = 0;              // tasks queued at or running on the helper
+    int admitting = 0;            // admit tasks among them (they hold slots)
+    bool helper_stop = false;
+    std::vector<Ticket*> ready;   // admitted and initialised, to join at the next tick
+    // solvers of completed tickets awaiting release (with the footprint each
+    // holds against the budget): freed by the worker between ticks, since
+    // freeing device memory waits for the whole device
+    using Releases = std::vector<std::pair<lbm3d_solver*, size_t>>;
+    Releases to_release;
     hipStream_t stream = nullptr;  // the ticks
-    hipStream_t side = nullptr;    // initialisation and read-back of solves outside the running tick
+    hipStream_t side = nullptr;    // the helper's initialisation and read-back
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     lbm3d::BatchPlan plans[3];  // one per precision
+    int64_t plan_ticks[3] = {0, 0, 0};  // ticks each plan has run since it was built
     lbm3d_server_counters stats{};  // guarded by mu
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void run();
+    void help();
+    void admit_one(Ticket* t);
     void finish(Ticket* t, int32_t status);
+    void to_helper(Ticket* t, int32_t status, bool admit)  // caller holds mu
+    {
+        tasks.push_back(Task{t, status, admit});
+        helping++;
+        if (admit) admitting++;
+        cv_help.notify_one();
+    }
 };
 
+static double secs_since(Clock::time_point a) { return std::chrono::duration<double>(Clock::now() - a).count(); }
+
+// Completes a ticket (helper thread): its results are read back on the side
+// stream, while a tick may run, and its solver is left to the worker to
+// free between ticks.
 void lbm3d_server::finish(Ticket* t, int32_t status)
 {
-    // caller holds no lock; the solver is only touched by the worker
+    const auto tf = Clock::now();
     if (t->h) {
         if (status == LBM3D_OK || status == LBM3D_E_NONFINITE) {
             const int64_t n = t->h->n;
@@ -79,29 +118,75 @@ void lbm3d_server::finish(Ticket* t, int32_t status)
         uint32_t hw = 0;
         (void)lbm3d_status(t->h, &hw, nullptr);
         t->health = hw;
-        (void)lbm3d_destroy(t->h);
-        t->h = nullptr;
     }
     std::lock_guard<std::mutex> lk(mu);
-    used -= t->footprint;
+    // (a ticket whose create failed still holds its footprint until then)
+    to_release.emplace_back(t->h, t->footprint);
+    t->h = nullptr;
     t->status = status;
     t->t_done = now();
     t->state = Ticket::DONE;
+    stats.completed++;
+    stats.finish_s += secs_since(tf);
     cv_done.notify_all();
+    cv_work.notify_one();
+}
+
+// Creates and initialises an admitted solve (helper thread); it joins the
+// active set at the worker's next tick.
+void lbm3d_server::admit_one(Ticket* t)
+{
+    const auto ta = Clock::now();
+    lbm3d_solver* h = nullptr;
+    int32_t rc = lbm3d_create(&t->p, &h);
+    if (rc == LBM3D_OK) rc = lbm3d_set_stream(h, side);
+    if (rc == LBM3D_OK)
+        rc = lbm3d_init(h, t->in[0].data(), t->in[1].data(), t->in[2].data(), t->in[3].data(), t->in[4].data());
+    for (auto& v : t->in) std::vector<double>().swap(v);
+    t->h = h;
+    if (rc != LBM3D_OK) {
+        finish(t, rc);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    t->t_admit = now();
+    t->state = Ticket::ACTIVE;
+    ready.push_back(t);
+    stats.admitted++;
+    stats.admit_s += secs_since(ta);
+    cv_work.notify_one();
+}
+
+void lbm3d_server::help()
+{
+    (void)hipSetDevice(device);
+    for (;;) {
+        Task task{nullptr, LBM3D_OK, false};
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_help.wait(lk, [&] { return !tasks.empty() || helper_stop; });
+            if (tasks.empty()) return;
+            task = tasks.front();
+            tasks.pop_front();
+        }
+        if (task.admit)
+            admit_one(task.t);
+        else
+            finish(task.t, task.status);
+        std::lock_guard<std::mutex> lk(mu);
+        helping--;
+        if (task.admit) admitting--;
+        cv_work.notify_one();
+    }
 }
 
 void lbm3d_server::run()
 {
     (void)hipSetDevice(device);
-    auto secs = [](Clock::time_point a) { return std::chrono::duration<double>(Clock::now() - a).count(); };
-    // Solves that finished at the last tick (done, failed, evicted or
-    // cancelled) with their status: read back and freed while the next tick
-    // runs.  Their memory stays counted against the budget until then.
-    std::vector<std::pair<Ticket*, int32_t>> finishing;
     for (;;) {
-        std::vector<Ticket*> admit;
         std::vector<Ticket*> act;
         bool rebuild = false;
+        Releases rel;
         {
             std::unique_lock<std::mutex> lk(mu);
             for (;;) {
@@ -118,137 +203,130 @@ void lbm3d_server::run()
                         ++it;
                     }
                 }
-                // admission in arrival order: by device footprint and slots
-                while (!queue.empty() && (int)(active.size() + admit.size()) < max_active &&
+                // admission in arrival order, by device footprint and slots
+                // (active, ready and being admitted): the helper creates and
+                // initialises the solve while the ticks run
+                while (!queue.empty() && (int)(active.size() + ready.size()) + admitting < max_active &&
                        used + queue.front()->footprint <= budget) {
                     Ticket* t = queue.front();
                     queue.pop_front();
                     used += t->footprint;
-                    admit.push_back(t);
+                    to_helper(t, LBM3D_OK, true);
+                }
+                // admitted solves join
+                if (!ready.empty()) {
+                    active.insert(active.end(), ready.begin(), ready.end());
+                    ready.clear();
+                    membership_changed = true;
                 }
                 // running tickets that were cancelled leave the active set
                 for (auto it = active.begin(); it != active.end();) {
                     if ((*it)->cancel) {
-                        finishing.emplace_back(*it, LBM3D_E_CANCELLED);
+                        to_helper(*it, LBM3D_E_CANCELLED, false);
                         it = active.erase(it);
                         membership_changed = true;
                     } else {
                         ++it;
                     }
                 }
-                if (!admit.empty() || !active.empty() || !finishing.empty() || stop) break;
+                rel.swap(to_release);
+                if (!active.empty() || !rel.empty()) break;
+                if (stop && queue.empty() && helping == 0 && ready.empty()) break;
                 cv_work.wait(lk);
             }
-            if (stop && admit.empty() && active.empty() && finishing.empty()) return;
             act = active;
             rebuild = membership_changed;
-            membership_changed = false;
+            if (!act.empty()) membership_changed = false;
         }
-        // 1. one tick of the active solves, enqueued without waiting: every
-        // precision group advances by the same number of steps, at most
-        // tick_steps and at most what its members still need.  A plan
-        // rebuilt for a new membership runs its first tick with direct
-        // launches; a graph is captured only for a membership that has
-        // lasted a tick (its replays then pay for the capture).
+        // 1. free the solvers of completed tickets: no tick is running
+        // (freeing waits for the device) and their footprint returns to the
+        // budget
+        if (!rel.empty()) {
+            const auto tr = Clock::now();
+            size_t freed = 0;
+            for (auto& r : rel) {
+                if (r.first) (void)lbm3d_destroy(r.first);
+                freed += r.second;
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            used -= freed;
+            stats.finish_s += secs_since(tr);
+        }
+        if (act.empty()) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (stop && queue.empty() && helping == 0 && ready.empty() && to_release.empty()) return;
+            continue;
+        }
+        // 2. one tick of the active solves: every precision group runs up
+        // to tick_steps launches of the batched step, in which each member
+        // takes the steps it still needs (at most tick_steps) and sits out
+        // the rest, so a solve that is about to finish does not shorten the
+        // tick for the others.  Ticks launch their steps directly; a graph
+        // is captured only for a membership that has lasted
+        // GRAPH_AFTER_TICKS ticks (capturing takes the worker milliseconds,
+        // during which the device waits, and arrivals and completions
+        // change the membership every few ticks under load).
         int32_t err = LBM3D_OK;
         double plan_s = 0.0;
         int rebuilds = 0;
         std::vector<Ticket*> members_of[3];
-        const bool ticking = !act.empty();
-        if (ticking) {
-            (void)hipEventRecord(ev0, stream);
-            for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++) {
-                std::vector<lbm3d_solver*> members;
-                int64_t k = tick_steps;
-                for (Ticket* t : act)
-                    if (t->h->mode == mode) {
-                        members.push_back(t->h);
-                        members_of[mode].push_back(t);
-                        k = std::min(k, t->left);
-                    }
-                if (members.empty() || k <= 0) continue;
-                const bool fresh = rebuild || plans[mode].ntiles() == 0;
-                if (fresh) {
-                    const auto tp = Clock::now();
-                    err = plans[mode].build(members, stream);
-                    plan_s += secs(tp);
-                    rebuilds++;
+        (void)hipEventRecord(ev0, stream);
+        for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++) {
+            std::vector<lbm3d_solver*> members;
+            std::vector<int64_t> limit;
+            int64_t k = 0;
+            for (Ticket* t : act)
+                if (t->h->mode == mode) {
+                    members.push_back(t->h);
+                    members_of[mode].push_back(t);
+                    limit.push_back(t->left);
+                    k = std::max(k, std::min(tick_steps, t->left));
                 }
-                if (err == LBM3D_OK) err = plans[mode].run(k, stream, !fresh);
-                if (err == LBM3D_OK)
-                    for (Ticket* t : members_of[mode]) t->left -= k;
+            if (members.empty() || k <= 0) continue;
+            const bool fresh = rebuild || plans[mode].ntiles() == 0;
+            if (fresh) {
+                const auto tp = Clock::now();
+                err = plans[mode].build(members, stream);
+                plan_s += secs_since(tp);
+                rebuilds++;
+                plan_ticks[mode] = 0;
             }
-            (void)hipEventRecord(ev1, stream);
+            const bool graphs = plan_ticks[mode]++ >= GRAPH_AFTER_TICKS;
+            if (err == LBM3D_OK) err = plans[mode].run(k, stream, graphs, &limit);
+            if (err == LBM3D_OK)
+                for (Ticket* t : members_of[mode]) t->left -= std::min(k, t->left);
         }
-        // 2. while the tick runs: allocate and initialise the admitted solves
-        // on the side stream (they join the next tick)
-        const auto ta = Clock::now();
-        int nadmit = 0;
-        for (Ticket* t : admit) {
-            lbm3d_solver* h = nullptr;
-            int32_t rc = lbm3d_create(&t->p, &h);
-            if (rc == LBM3D_OK) rc = lbm3d_set_stream(h, side);
-            if (rc == LBM3D_OK)
-                rc = lbm3d_init(h, t->in[0].data(), t->in[1].data(), t->in[2].data(), t->in[3].data(),
-                                t->in[4].data());
-            for (auto& v : t->in) std::vector<double>().swap(v);
-            t->h = h;
-            if (rc != LBM3D_OK) {
-                finishing.emplace_back(t, rc);
-                continue;
-            }
-            std::lock_guard<std::mutex> lk(mu);
-            t->t_admit = now();
-            t->state = Ticket::ACTIVE;
-            active.push_back(t);
-            membership_changed = true;
-            nadmit++;
-        }
-        const double admit_s = admit.empty() ? 0.0 : secs(ta);
-        // 3. while the tick runs: read back and free the solves that finished
-        // at the previous tick (read-back on the side stream; freeing waits
-        // for the device)
-        const auto tf = Clock::now();
-        const size_t nfinish = finishing.size();
-        for (auto& ts : finishing) finish(ts.first, ts.second);
-        finishing.clear();
-        const double finish_s = nfinish ? secs(tf) : 0.0;
-        // 4. wait for the tick, then the health of every member (one gather
+        (void)hipEventRecord(ev1, stream);
+        // 3. wait for the tick, then the health of every member (one gather
         // per precision): a solve that has gone non-finite stops now instead
-        // of running out its steps
+        // of running out its steps; finished solves go to the helper
         float busy_ms = 0.0f;
         int nevict = 0;
-        if (ticking) {
-            if (err == LBM3D_OK && hipStreamSynchronize(stream) != hipSuccess) err = LBM3D_E_DEVICE;
-            if (err == LBM3D_OK) (void)hipEventElapsedTime(&busy_ms, ev0, ev1);
-            std::vector<uint32_t> hw_of[3];
-            for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++)
-                if (!members_of[mode].empty()) err = plans[mode].health(hw_of[mode], stream);
-            std::lock_guard<std::mutex> lk(mu);
-            for (int mode = 0; mode < 3; mode++) {
-                for (size_t j = 0; j < members_of[mode].size(); j++) {
-                    Ticket* t = members_of[mode][j];
-                    const uint32_t hw = (err == LBM3D_OK && j < hw_of[mode].size()) ? hw_of[mode][j] : 0u;
-                    const bool bad = (hw & LBM3D_HEALTH_NONFINITE) != 0;
-                    if (err == LBM3D_OK && t->left > 0 && !bad) continue;
-                    auto it = std::find(active.begin(), active.end(), t);
-                    if (it != active.end()) active.erase(it);
-                    membership_changed = true;
-                    if (bad && t->left > 0) nevict++;
-                    finishing.emplace_back(t, err != LBM3D_OK ? err : (bad ? LBM3D_E_NONFINITE : LBM3D_OK));
-                }
+        if (err == LBM3D_OK && hipStreamSynchronize(stream) != hipSuccess) err = LBM3D_E_DEVICE;
+        if (err == LBM3D_OK) (void)hipEventElapsedTime(&busy_ms, ev0, ev1);
+        std::vector<uint32_t> hw_of[3];
+        for (int mode = 0; mode < 3 && err == LBM3D_OK; mode++)
+            if (!members_of[mode].empty()) err = plans[mode].health(hw_of[mode], stream);
+        std::lock_guard<std::mutex> lk(mu);
+        for (int mode = 0; mode < 3; mode++) {
+            for (size_t j = 0; j < members_of[mode].size(); j++) {
+                Ticket* t = members_of[mode][j];
+                const uint32_t hw = (err == LBM3D_OK && j < hw_of[mode].size()) ? hw_of[mode][j] : 0u;
+                const bool bad = (hw & LBM3D_HEALTH_NONFINITE) != 0;
+                if (err == LBM3D_OK && t->left > 0 && !bad) continue;
+                auto it = std::find(active.begin(), active.end(), t);
+                if (it == active.end()) continue;  // (already handed over, cancelled)
+                active.erase(it);
+                membership_changed = true;
+                if (bad && t->left > 0) nevict++;
+                to_helper(t, err != LBM3D_OK ? err : (bad ? LBM3D_E_NONFINITE : LBM3D_OK), false);
             }
         }
-        std::lock_guard<std::mutex> lk(mu);
-        if (ticking) stats.ticks++;
+        stats.ticks++;
         stats.rebuilds += rebuilds;
         stats.plan_s += plan_s;
         stats.busy_s += busy_ms * 1e-3;
-        stats.admitted += nadmit;
-        stats.completed += (int64_t)nfinish;
         stats.evicted += nevict;
-        stats.admit_s += admit_s;
-        stats.finish_s += finish_s;
     }
 }
 
@@ -274,8 +352,17 @@ int32_t lbm3d_server_create(size_t hbm_budget_bytes, int32_t max_active, lbm3d_s
         return LBM3D_E_DEVICE;
     }
     try {
+        s->helper = std::thread([s] { s->help(); });
         s->worker = std::thread([s] { s->run(); });
     } catch (...) {
+        if (s->helper.joinable()) {
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->helper_stop = true;
+                s->cv_help.notify_one();
+            }
+            s->helper.join();
+        }
         (void)hipEventDestroy(s->ev0);
         (void)hipEventDestroy(s->ev1);
         (void)hipStreamDestroy(s->side);
@@ -402,7 +489,15 @@ int32_t lbm3d_server_destroy(lbm3d_server_t s)
         for (auto& kv : s->tickets) kv.second->cancel = true;
         s->cv_work.notify_one();
     }
+    // the worker returns once every ticket is complete and every solver
+    // freed (the helper has no task left then)
     if (s->worker.joinable()) s->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->helper_stop = true;
+        s->cv_help.notify_one();
+    }
+    if (s->helper.joinable()) s->helper.join();
     (void)hipStreamSynchronize(s->stream);
     (void)hipStreamSynchronize(s->side);
     for (auto& pl : s->plans) pl.build({}, s->stream);  // drop the plans' graphs and tables first

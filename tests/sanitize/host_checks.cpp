@@ -26,9 +26,12 @@ hipError_t launch_ghosts(int, const Grid&, const FaceBC&, const Model<double>&, 
 hipError_t launch_moments(int, const Grid&, const Model<double>&, const void*, double*, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_conserved(int, const Grid&, const Model<double>&, const void*, double*, int, double*, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_pack(int, const Grid&, const void*, void*, bool, hipStream_t) { return hipErrorNoDevice; }
-hipError_t launch_batch_layers(int, const BatchSolve*, const BatchLayerJob*, const int32_t*, int, int, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_batch_layers(int, const BatchSolve*, const BatchLayerJob*, const int32_t*, int, int, const BatchCount*,
+                               hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_batch_count(BatchCount*, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_gather_health(const BatchSolve*, int, uint32_t*, hipStream_t) { return hipErrorNoDevice; }
-hipError_t launch_batch_step(int, int, bool, const BatchSolve*, const BatchTile*, BatchQueue*, int, int, int, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_batch_step(int, int, bool, const BatchSolve*, const BatchTile*, BatchQueue*, int, int, int,
+                             const BatchCount*, hipStream_t) { return hipErrorNoDevice; }
 }  // namespace lbm3d
 
 extern "C" int32_t lbm3d_stream_copy_rate(int64_t, int32_t, double*) { return LBM3D_E_DEVICE; }
