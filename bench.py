@@ -14,7 +14,8 @@ a captured graph.
 Beside it:
   roofline      the fused step kernel's algorithmic HBM rate (15 reads + 15
                 writes of f per node) over its mean launch time, measured with
-                HIP events around each launch, against the 8 TB/s peak;
+                HIP events that each launch's dispatch records at its start
+                and end, against the 8 TB/s peak;
                 `traffic` is the counter-measured HBM bytes per launch from
                 the committed rocprofv3 summary when it was taken on this
                 kernel source, else null;
@@ -459,7 +460,8 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = ms / args.steps
     mlups = case.sites * args.steps / (ms / 1e3) / 1e6
-    # per-launch duration of the fused step kernel (events around each launch)
+    # per-launch duration of the fused step kernel (events recorded by each
+    # launch's dispatch)
     _, kernel_ms = s.step_profiled(min(200, args.steps))
     health, done = s.status()
     if args.copy_check:

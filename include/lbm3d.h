@@ -156,10 +156,12 @@ int32_t lbm3d_step(lbm3d_t h, int64_t nsteps);
 int32_t lbm3d_step_timed(lbm3d_t h, int64_t nsteps, double* ms);
 
 /* Measurement run: enqueue nsteps steps one launch at a time (no graph),
- * recording HIP events on the handle's stream around every launch of the
- * fused step kernel, then wait.  *total_ms receives the device time of all
- * nsteps steps, *step_kernel_ms the mean duration of one fused-step launch
- * (either pointer may be NULL).  The state advances exactly as lbm3d_step. */
+ * each launch of the fused step kernel recording HIP events at its own
+ * start and end (hipExtLaunchKernel: the dispatch records them, so no
+ * separate markers surround the kernel), then wait.  *total_ms receives
+ * the device time of all nsteps steps, *step_kernel_ms the mean duration
+ * of one fused-step launch (either pointer may be NULL).  The state
+ * advances exactly as lbm3d_step. */
 int32_t lbm3d_step_profiled(lbm3d_t h, int64_t nsteps, double* total_ms, double* step_kernel_ms);
 
 /* Launch shape of the fused step kernel: a tile is 64 x `by` nodes in x-y

@@ -3,6 +3,8 @@
 // checkpoint pack/unpack.
 #include "lbm3d_tile.h"
 
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 namespace lbm3d {
@@ -503,7 +505,7 @@ hipError_t launch_init(int mode, const Grid& g, const Model<double>& md, const d
 template <int MODE, int BY>
 static void launch_tiled(const Grid& g, const FaceBC& bc, int tz, bool stream, const Model<double>& md,
                          const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
-                         uint32_t* health, hipStream_t s)
+                         uint32_t* health, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     using S = typename Types<MODE>::S;
     const int ntx = (g.nx + TILE_X - 1) / TILE_X;
@@ -517,35 +519,65 @@ static void launch_tiled(const Grid& g, const FaceBC& bc, int tz, bool stream, c
     A.fn = (S*)fn;
     A.health = health;
     x_fixed_states(inflow, A.xin);
-    if (stream)
-        k_step_tiled<MODE, BY, true><<<dim3(nb), dim3(TILE_X * BY), 0, s>>>(A, md, mf, ntx, nty, tz);
-    else
-        k_step_tiled<MODE, BY, false><<<dim3(nb), dim3(TILE_X * BY), 0, s>>>(A, md, mf, ntx, nty, tz);
+    const dim3 grid(nb), block(TILE_X * BY);
+    if (e0 || e1) {
+        if (stream)
+            hipExtLaunchKernelGGL(k_step_tiled<MODE, BY, true>, grid, block, 0, s, e0, e1, 0, A, md, mf, ntx, nty, tz);
+        else
+            hipExtLaunchKernelGGL(k_step_tiled<MODE, BY, false>, grid, block, 0, s, e0, e1, 0, A, md, mf, ntx, nty,
+                                  tz);
+    } else if (stream) {
+        k_step_tiled<MODE, BY, true><<<grid, block, 0, s>>>(A, md, mf, ntx, nty, tz);
+    } else {
+        k_step_tiled<MODE, BY, false><<<grid, block, 0, s>>>(A, md, mf, ntx, nty, tz);
+    }
+}
+
+template <int MODE>
+static void launch_untiled(dim3 grid, dim3 block, bool upwind2, const Grid& g, const Model<double>& md,
+                           const Model<float>& mf, const void* f, void* fn, uint32_t* health, hipStream_t s,
+                           hipEvent_t e0, hipEvent_t e1)
+{
+    using S = typename Types<MODE>::S;
+    const S* fi = (const S*)f;
+    S* fo = (S*)fn;
+    if (e0 || e1) {
+        if (upwind2)
+            hipExtLaunchKernelGGL(k_step<MODE, true>, grid, block, 0, s, e0, e1, 0, g, md, mf, fi, fo, health);
+        else
+            hipExtLaunchKernelGGL(k_step<MODE, false>, grid, block, 0, s, e0, e1, 0, g, md, mf, fi, fo, health);
+    } else if (upwind2) {
+        k_step<MODE, true><<<grid, block, 0, s>>>(g, md, mf, fi, fo, health);
+    } else {
+        k_step<MODE, false><<<grid, block, 0, s>>>(g, md, mf, fi, fo, health);
+    }
 }
 
 hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg& tc, const Model<double>& md,
                        const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
-                       uint32_t* health, hipStream_t s, bool upwind2)
+                       uint32_t* health, hipStream_t s, bool upwind2, hipEvent_t e0, hipEvent_t e1)
 {
     if (upwind2 && tc.by != 0) return hipErrorInvalidValue;
     if (tc.by != 0) {
         switch (tc.by) {
-        case 2: LBM3D_DISPATCH(mode, launch_tiled<MD, 2>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s)); break;
+        case 2:
+            LBM3D_DISPATCH(mode, launch_tiled<MD, 2>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s, e0, e1));
+            break;
         case 8:
             if (mode == MODE_FP64) return hipErrorInvalidValue;
-            if (mode == MODE_FP32) launch_tiled<MODE_FP32, 8>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s);
-            else launch_tiled<MODE_FP32_T64, 8>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s);
+            if (mode == MODE_FP32)
+                launch_tiled<MODE_FP32, 8>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s, e0, e1);
+            else
+                launch_tiled<MODE_FP32_T64, 8>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s, e0, e1);
             break;
-        default: LBM3D_DISPATCH(mode, launch_tiled<MD, 4>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s)); break;
+        default:
+            LBM3D_DISPATCH(mode, launch_tiled<MD, 4>(g, bc, tc.tz, tc.stream, md, mf, inflow, f, fn, health, s, e0, e1));
+            break;
         }
         return hipGetLastError();
     }
-    dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, g.nz);
-    if (upwind2) {
-        LBM3D_DISPATCH(mode, k_step<MD, true><<<grid, dim3(TX, TY), 0, s>>>(g, md, mf, (const typename Types<MD>::S*)f, (typename Types<MD>::S*)fn, health));
-    } else {
-        LBM3D_DISPATCH(mode, k_step<MD, false><<<grid, dim3(TX, TY), 0, s>>>(g, md, mf, (const typename Types<MD>::S*)f, (typename Types<MD>::S*)fn, health));
-    }
+    const dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, g.nz), block(TX, TY);
+    LBM3D_DISPATCH(mode, launch_untiled<MD>(grid, block, upwind2, g, md, mf, f, fn, health, s, e0, e1));
     return hipGetLastError();
 }
 

@@ -143,9 +143,13 @@ bool tiled_fits(int mode, const Grid& g);
 // faces need no layers in memory.
 uint32_t ghost_faces(const Grid& g, const FaceBC& bc, bool tiled);
 // upwind2: the second-order upwind variant (untiled kernel only: tc.by == 0)
+// ev_start / ev_stop (optional): events that the kernel's own dispatch
+// records at its start and end (hipExtLaunchKernel), for timing the kernel
+// without markers of their own around it.
 hipError_t launch_step(int mode, const Grid& g, const FaceBC& bc, const TileCfg& tc, const Model<double>& md,
                        const Model<float>& mf, const double (*inflow)[5], const void* f, void* fn,
-                       uint32_t* health, hipStream_t s, bool upwind2 = false);
+                       uint32_t* health, hipStream_t s, bool upwind2 = false, hipEvent_t ev_start = nullptr,
+                       hipEvent_t ev_stop = nullptr);
 // (rho, ux, uy, uz, T) of the two x faces' fixed states, from the ABI's
 // (rho, ux, uy, uz, p)
 void x_fixed_states(const double (*inflow)[5], double (&xin)[2][5]);

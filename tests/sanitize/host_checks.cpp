@@ -20,7 +20,8 @@
 namespace lbm3d {
 hipError_t launch_init(int, const Grid&, const Model<double>&, const double*, void*, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_step(int, const Grid&, const FaceBC&, const TileCfg&, const Model<double>&, const Model<float>&,
-                       const double (*)[5], const void*, void*, uint32_t*, hipStream_t, bool) { return hipErrorNoDevice; }
+                       const double (*)[5], const void*, void*, uint32_t*, hipStream_t, bool, hipEvent_t,
+                       hipEvent_t) { return hipErrorNoDevice; }
 hipError_t launch_ghosts(int, const Grid&, const FaceBC&, const Model<double>&, const double (*)[5], bool, void*,
                          hipStream_t, uint32_t) { return hipErrorNoDevice; }
 hipError_t launch_moments(int, const Grid&, const Model<double>&, const void*, double*, hipStream_t) { return hipErrorNoDevice; }
