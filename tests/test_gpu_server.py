@@ -137,6 +137,31 @@ def test_cancel_queued_ticket():
             srv2.close()
 
 
+def test_cancel_running_ticket_and_close_with_work_in_flight():
+    """A running solve cancelled between ticks stops with E_CANCELLED after
+    some of its steps, and the solve beside it is bitwise its solo run;
+    closing the server with solves running and queued cancels them and
+    returns (the helper thread that admits and reads back drains first)."""
+    lbm3d = _lib()
+    long = inputs.riemann_3d(13, grid=(64, 64, 64), precision="fp32_t64")
+    short = inputs.riemann_3d(14, grid=(32, 32, 32), precision="fp32_t64")
+    with lbm3d.Server(8 << 30, 4, tick_steps=8) as srv:
+        t1 = srv.submit(long.params, long.fields, 1000000)
+        t2 = srv.submit(short.params, short.fields, 50)
+        rc2, f2, tm2 = srv.wait(t2, _shape(short))
+        srv.cancel(t1)
+        rc1, _, tm1 = srv.wait(t1, _shape(long))
+        assert rc2 == lbm3d.OK and tm2["steps"] == 50
+        assert rc1 == lbm3d.E_CANCELLED and 0 < tm1["steps"] < 1000000
+        for a, b in zip(f2, _alone(short, 50)):
+            assert np.array_equal(a, b)
+        for _ in range(3):
+            srv.submit(long.params, long.fields, 1000000)
+        st = srv.stats()
+        assert st["admitted"] >= 2
+    # (the with-block closed the server with those three in flight)
+
+
 def _unstable_case(precision="fp32", flags=0):
     """(c1, c2, eta0) = (2, 6, 2) at the post-shock state of a Mach-8 shock,
     slightly perturbed: admitted by the Courant and diffusion numbers but
