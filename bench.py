@@ -47,6 +47,7 @@ Beside it:
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--seed S]
                   [--no-batch] [--no-serve] [--no-cpu-baseline] [--copy-check]
                   [--batch-only] [--serve-requests N] [--stores auto|non-temporal|plain]
+                  [--grid NX NY NZ]
 """
 from __future__ import annotations
 
@@ -66,6 +67,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, vendor figure
 BYTES_PER_SITE = {"fp64": 240, "fp32": 120, "fp32_t64": 120}  # 15 reads + 15 writes of f
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_hbm_traffic.txt")
+HEADLINE_GRID = (256, 128, 128)
 KERNEL_SOURCES = ["lbm3d_tile.h", "lbm3d_model.h", "lbm3d_device.hip", "lbm3d_internal.h", "lbm3d_layout.cpp"]
 
 
@@ -407,6 +409,9 @@ def main():
                          "pinned after tuning (for profiles taken with a known kind)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched step of the 64-solve mix (--steps steps) and print its rate")
+    ap.add_argument("--grid", type=int, nargs=3, default=list(HEADLINE_GRID), metavar=("NX", "NY", "NZ"),
+                    help="grid of the shock-bubble workload (default: the headline 256 128 128); other grids "
+                         "are for shape studies: no counter traffic and no CPU baseline are reported for them")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -436,7 +441,8 @@ def main():
                           "tile": [64, 8, tz], "batched_mlups": round(sites * args.steps / dt / 1e6, 1)}), flush=True)
         return
 
-    case = inputs.shock_bubble(args.seed, precision=args.precision)
+    headline = tuple(args.grid) == HEADLINE_GRID
+    case = inputs.shock_bubble(args.seed, grid=tuple(args.grid), precision=args.precision)
     nx, ny, nz = case.grid
     s = lbm3d.Solver(case.params)
     s.init(*case.fields)
@@ -497,7 +503,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.precision, stores),
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": measured_traffic(args.precision, stores) if headline else None,
             "kernel": "k_step_tiled", "kernel_ms": round(kernel_ms, 5), "bytes_per_site": bps,
             "sites_per_launch": case.sites,
         },
@@ -517,7 +524,7 @@ def main():
         out["batch"] = batch_bench(lbm3d, inputs, metrics, args.seed)
     if not args.no_serve:
         out["serving"] = serve_bench(lbm3d, inputs, metrics, args.seed, count=args.serve_requests)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and headline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)
 
