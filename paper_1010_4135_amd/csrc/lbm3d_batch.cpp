@@ -28,17 +28,6 @@ constexpr double TILE_PROLOGUE_PLANES = 3.0;
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-static int device_cus()
-{
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-            cus = prop.multiProcessorCount;
-    }
-    return cus;
-}
-
 int32_t plan_tiles(const std::vector<Grid>& grids, int by, int tz, int cus, TilePlan& out)
 {
     out = TilePlan();

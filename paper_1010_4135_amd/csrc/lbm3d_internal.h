@@ -133,6 +133,8 @@ struct TileCfg {
 // streaming keeps the L2 for the halo planes.  The autotuner tries both.
 constexpr int64_t STREAM_MIN_BYTES = (int64_t)320 << 20;
 TileCfg default_tile(int mode, const Grid& g);
+// compute units of the current device (256 when it cannot be asked)
+int device_cus();
 bool tile_supported(int mode, const Grid& g, const TileCfg& t);
 // the tiled kernels (single and batched) take this solve
 bool tiled_fits(int mode, const Grid& g);

@@ -5,6 +5,8 @@
 #include "lbm3d_model.h"
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 namespace lbm3d {
 
@@ -92,21 +94,66 @@ bool tiled_fits(int mode, const Grid& g)
     return (g.plane_major ? g.len : g.sv) * es < ((int64_t)1 << 31);
 }
 
+int device_cus()
+{
+    static std::mutex mu;
+    static std::vector<int> cache;  // per device, 0 until looked up
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if ((size_t)dev >= cache.size()) cache.resize((size_t)dev + 1, 0);
+    if (!cache[(size_t)dev]) {
+        int cus = 256;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+        cache[(size_t)dev] = cus;
+    }
+    return cache[(size_t)dev];
+}
+
 TileCfg default_tile(int mode, const Grid& g)
 {
-    // measured on MI355X at 256x128x128: 64x8x32 tiles (FP32 modes) and
-    // 64x4x64 (FP64); a short z extent leaves too few workgroups on small grids
+    // Tiles of 64 x BY columns (BY = 8 in the FP32 modes, 4 in FP64, the
+    // rows that fit two wavefronts per SIMD) and a z-chunk depth from a
+    // simple launch model: the tiles run in rounds of one per compute unit,
+    // and a tile takes time in proportion to its planes plus the four
+    // planes its z ring loads first; the depth with the lowest cost wins
+    // (the longer one on a tie).  When even the shortest useful chunks (8
+    // planes) leave more than a quarter of the compute units without a
+    // tile, the untiled kernel, whose small blocks spread over all of
+    // them, is faster.  These choices match the autotuner's on the grids it
+    // was compared on (256x128x128, 192x128x128, 128^3 and the paper's
+    // 298x78x78 tile; grids up to 96x64x64 in the FP32 modes and up to 64^3
+    // in FP64 untiled), which remains the way to the best shape.
     TileCfg t;
-    if (!tiled_fits(mode, g)) {
-        t.by = 0;
-        t.tz = 1;
-        return t;
-    }
-    t.by = mode == MODE_FP64 ? 4 : 8;
-    t.tz = mode == MODE_FP64 ? 64 : 32;
+    t.by = 0;
+    t.tz = 1;
+    if (!tiled_fits(mode, g)) return t;
     const int64_t es = mode == MODE_FP64 ? 8 : 4;
     t.stream = 2 * g.len * es > STREAM_MIN_BYTES;
-    if (g.nz < 2 * t.tz) t.tz = std::max(2, g.nz / 4);
+    const int by = mode == MODE_FP64 ? 4 : 8;
+    const int64_t cus = device_cus();
+    const int64_t cols = (int64_t)((g.nx + TILE_X - 1) / TILE_X) * ((g.ny + by - 1) / by);
+    int best_tz = 0;
+    int64_t best_cost = 0, best_tiles = 0;
+    for (int64_t tz = 8;; tz *= 2) {
+        const int64_t d = std::min<int64_t>(tz, g.nz);
+        const int64_t tiles = cols * ((g.nz + d - 1) / d);
+        const int64_t cost = ((tiles + cus - 1) / cus) * (d + 4);
+        if (best_tz == 0 || cost <= best_cost) {
+            best_tz = (int)d;
+            best_cost = cost;
+            best_tiles = tiles;
+        }
+        if (d >= g.nz) break;
+    }
+    if (4 * best_tiles < 3 * cus) return t;  // untiled
+    t.by = by;
+    t.tz = best_tz;
     return t;
 }
 

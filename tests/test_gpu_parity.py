@@ -100,9 +100,20 @@ def _small_cases():
     return out
 
 
+@pytest.mark.parametrize("tile", [None, (4, 3)], ids=["default_shape", "tiles_64x4x3"])
 @pytest.mark.parametrize("name,case,steps", _small_cases(), ids=[c[0] for c in _small_cases()])
-def test_fp64_matches_oracle_small(name, case, steps):
-    s, mg = gpu_run(case, steps, precision="fp64")
+def test_fp64_matches_oracle_small(name, case, steps, tile):
+    """Small grids against the oracle, at the default launch shape (the
+    untiled kernel for most of them) and with 64 x 4 x 3 tiles (ragged in
+    every axis)."""
+    prm = dict(case.params)
+    prm["precision"] = "fp64"
+    s = _lib().Solver(prm)
+    if tile is not None:
+        s.set_tile(*tile)
+    s.init(*case.fields)
+    s.step(steps)
+    mg = s.moments()
     o, mo = oracle_run(case, steps)
     err = metrics.rel_l1(mg, mo)
     _report(name, err)
