@@ -293,7 +293,8 @@ def serve_bench(lbm3d, inputs, metrics, seed: int, count: int = 200):
       back to back (create, init, step, read back, free), which gives each
       request's service time, the FP64 results and the baseline capacity;
       the same loop in the served precision gives the capacity ratio at
-      equal precision;
+      equal precision, and each of its results is compared bit for bit
+      with the served one;
     - at 50%, 80% and 95% of the served capacity: the served path on the
       open stream, measured; the baseline's latencies are its measured
       service times replayed through the FIFO queue of the same arrival
@@ -332,17 +333,22 @@ def serve_bench(lbm3d, inputs, metrics, seed: int, count: int = 200):
             base.append(s.moments())
         service.append(time.perf_counter() - t0)
     base_capacity = count / sum(service)
+    res_cap, _, w_cap, st_cap = served(1e12)
+    capacity = count / w_cap
     # the same loop in the served precision, to separate what serving gains
-    # from what FP32 storage gains
-    t0 = time.perf_counter()
-    for _, c in base_trace:
+    # from what FP32 storage gains; each result is compared bit for bit with
+    # the served one (outside the loop's timing)
+    t_same, same_bits = 0.0, 0
+    for k, (_, c) in enumerate(base_trace):
+        t0 = time.perf_counter()
         with lbm3d.Solver(dict(c.params, precision="fp32_t64")) as s:
             s.init(*c.fields)
             s.step(c.steps)
-            s.moments()
-    same_capacity = count / (time.perf_counter() - t0)
-    _, _, w_cap, st_cap = served(1e12)
-    capacity = count / w_cap
+            m = s.moments()
+        t_same += time.perf_counter() - t0
+        same_bits += all(np.array_equal(a, b) for a, b in zip(m, res_cap[k]))
+    del res_cap
+    same_capacity = count / t_same
     out = {"requests": count, "served_precision": "fp32_t64",
            "baseline": "one solve at a time, FP64, arrival order; latencies from its measured service times "
                        "replayed through the FIFO queue of the arrival trace",
@@ -351,6 +357,7 @@ def serve_bench(lbm3d, inputs, metrics, seed: int, count: int = 200):
            "capacity_ratio": round(capacity / base_capacity, 3),
            "same_precision_loop_capacity_solves_per_s": round(same_capacity, 3),
            "capacity_ratio_same_precision": round(capacity / same_capacity, 3),
+           "served_bitwise_equal_alone": f"{same_bits}/{count}",
            "capacity_run_busy_frac": round(st_cap["busy_s"] / max(w_cap, 1e-9), 3)}
     grids = sorted({c.grid for _, c in base_trace})
     levels = []
