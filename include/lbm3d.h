@@ -330,8 +330,9 @@ int32_t lbm3d_batch_step_noalloc(lbm3d_t* hs, int32_t count, const int64_t* nste
 
 /* Work plan of the batched step, computed on the host (no device work): the
  * tiles of solves with parameters ps[0..count-1] (validated as lbm3d_create,
- * all of one precision) at tile depth tz (<= 0: the tuned or default depth;
- * a depth at or beyond a solve's nz gives whole columns), for a device of
+ * all of one precision) at tile depth tz (0: the tuned depth of the
+ * precision, else a launch model's for these solves; < 0: the model's; a
+ * depth at or beyond a solve's nz gives whole columns), for a device of
  * `cus` compute units.  Tiles are 64 x BY nodes in x-y (BY = 4 in FP64, 8
  * otherwise).  Each solve's tiles are cut into contiguous row slabs, the
  * slabs are dealt to up to 8 lists (one per XCD) largest first onto the
@@ -353,14 +354,18 @@ int32_t lbm3d_batch_plan(const lbm3d_params* ps, int32_t count, int32_t tz, int3
  * saved to temporary device memory and restored afterwards (states
  * unchanged; without memory for the copies each trial recomputes the
  * current levels), and keeps the depth with the fastest round for every later batched
- * step (lbm3d_batch_step and servers) of that precision in this process.
+ * step (lbm3d_batch_step) of that precision in this process.  Servers do
+ * not use it: their membership changes from tick to tick, and each of
+ * their plans takes the launch model's depth for its members (the
+ * persistent workgroups share the tiles' planes, and no launch ends before
+ * its longest tile).
  * Blocking.  *tz (may be NULL) receives the depth. */
 int32_t lbm3d_batch_tune(lbm3d_t* hs, int32_t count, int32_t launches, int32_t* tz);
 
-/* Tile depth of later batched steps (lbm3d_batch_step, servers) of one
- * precision in this process, as the autotuner would set it; 0 restores the
- * default (32).  Results do not depend on it.  E_INVAL for a bad precision
- * or tz outside [0, 65535]. */
+/* Tile depth of later batched steps (lbm3d_batch_step) of one precision
+ * in this process, as the autotuner would set it; 0 restores the default
+ * (the launch model's depth for each batch).  Results do not depend on it.
+ * E_INVAL for a bad precision or tz outside [0, 65535]. */
 int32_t lbm3d_batch_set_depth(int32_t precision, int32_t tz);
 
 /* ------------------------------------------------------------- serving --- */

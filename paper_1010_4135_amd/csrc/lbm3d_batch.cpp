@@ -20,8 +20,6 @@ static int32_t herr(hipError_t e)
 
 // Steps per captured graph of the batched step (even: parities 0,1,...).
 constexpr int BATCH_GRAPH_STEPS = 16;
-// Tile depth of the batched step before any tuning.
-constexpr int BATCH_DEFAULT_TZ = 32;
 // Planes a tile marches before its first update (the z prologue), counted
 // in the cost that balances the lists.
 constexpr double TILE_PROLOGUE_PLANES = 3.0;
@@ -138,10 +136,49 @@ void BatchPlan::release_graph()
     graph_ = nullptr;
 }
 
-static int plan_depth(int mode, int tz)
+// Tile depth from a launch model of a membership: the persistent
+// workgroups share the tiles' work (each tile's planes plus the planes its
+// z ring loads first), and no launch ends before its longest tile.  The
+// depth (16, 32, ... up to whole columns) with the lowest estimate wins,
+// the deeper one on a tie: whole columns for a batch as large as the
+// 64-solve mix (as the tuner finds), short chunks for a few solves, whose
+// whole columns would leave most compute units idle.
+static int model_depth(const std::vector<Grid>& grids, int by, int cus)
 {
-    int t = tz > 0 ? tz : batch_tile_depth(mode);
-    return t > 0 ? t : BATCH_DEFAULT_TZ;
+    int maxnz = 1;
+    for (const Grid& g : grids) maxnz = std::max(maxnz, g.nz);
+    int best = 0;
+    double best_t = 0.0;
+    for (int d = 16;; d *= 2) {
+        const int dd = std::min(d, maxnz);
+        double work = 0.0, longest = 0.0;
+        for (const Grid& g : grids) {
+            const double cols = (double)((g.nx + TILE_X - 1) / TILE_X) * ((g.ny + by - 1) / by);
+            const double chunks = (double)((g.nz + dd - 1) / dd);
+            work += cols * (g.nz + TILE_PROLOGUE_PLANES * chunks);
+            longest = std::max(longest, std::min(dd, g.nz) + TILE_PROLOGUE_PLANES);
+        }
+        const double t = std::max(work / cus, longest);
+        if (best == 0 || t <= best_t) {
+            best = dd;
+            best_t = t;
+        }
+        if (dd >= maxnz) break;
+    }
+    return best;
+}
+
+// Tile depth of a plan: tz > 0 as given; 0: the precision's tuned depth,
+// else the model's; < 0: the model's (memberships that change from tick to
+// tick, whose best depth no earlier tuning knows).
+static int plan_depth(int mode, int tz, const std::vector<Grid>& grids, int by, int cus)
+{
+    if (tz > 0) return tz;
+    if (tz == 0) {
+        const int t = batch_tile_depth(mode);
+        if (t > 0) return t;
+    }
+    return model_depth(grids, by, cus);
 }
 
 // layer jobs of the members (faces the tiles leave to memory)
@@ -192,7 +229,8 @@ size_t BatchPlan::table_bytes(const std::vector<lbm3d_solver*>& members, int tz)
     std::vector<Grid> grids;
     for (lbm3d_solver* h : members) grids.push_back(h->g);
     TilePlan p;
-    if (plan_tiles(grids, by, plan_depth(mode, tz), device_cus(), p) != LBM3D_OK) return (size_t)-1;
+    const int cus = device_cus();
+    if (plan_tiles(grids, by, plan_depth(mode, tz, grids, by, cus), cus, p) != LBM3D_OK) return (size_t)-1;
     std::vector<uint32_t> rest;
     std::vector<BatchLayerJob> lj;
     std::vector<int32_t> bj;
@@ -219,10 +257,11 @@ int32_t BatchPlan::build(const std::vector<lbm3d_solver*>& members, hipStream_t 
     int64_t level_bytes = 0;
     for (lbm3d_solver* h : members) level_bytes += 2 * (int64_t)f_bytes(h->g, h->mode);
     stream_ = level_bytes > STREAM_MIN_BYTES;
-    tz_ = plan_depth(mode_, tz);
     std::vector<Grid> grids;
     for (lbm3d_solver* h : members) grids.push_back(h->g);
-    int32_t rc = plan_tiles(grids, by_, tz_, device_cus(), plan_);
+    const int cus = device_cus();
+    tz_ = plan_depth(mode_, tz, grids, by_, cus);
+    int32_t rc = plan_tiles(grids, by_, tz_, cus, plan_);
     if (rc) return rc;
 
     std::vector<BatchSolve> table(members.size());
@@ -528,7 +567,7 @@ extern "C" int32_t lbm3d_batch_plan(const lbm3d_params* ps, int32_t count, int32
     const int mode = ps[0].precision;
     const int by = mode == LBM3D_FP64 ? 4 : 8;
     TilePlan p;
-    int32_t rc = plan_tiles(grids, by, plan_depth(mode, tz), cus, p);
+    int32_t rc = plan_tiles(grids, by, plan_depth(mode, tz, grids, by, cus), cus, p);
     if (rc) return rc;
     const int64_t n = (int64_t)p.tiles.size();
     if (ntiles) *ntiles = (int32_t)n;

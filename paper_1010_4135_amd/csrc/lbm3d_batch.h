@@ -36,14 +36,15 @@ public:
 
     // (Re)build for `members` (all initialised, same precision); each
     // member's current buffer is taken as parity 0.  Enqueued on `s`.
-    // `tz` > 0 sets the tile depth, else the tuned or default one is used.
+    // `tz` > 0 sets the tile depth; 0 takes the tuned depth of the
+    // precision, else the launch model's; < 0 the launch model's.
     // The device tables go into a buffer the plan allocates, or, with
     // `dev` != nullptr, into the caller's `cap` bytes at `dev` (then nothing
     // is allocated and E_NOMEM is returned if they do not fit).
     int32_t build(const std::vector<lbm3d_solver*>& members, hipStream_t s, int tz = 0,
                   void* dev = nullptr, size_t cap = 0);
     // Device bytes the tables of `members` need at tile depth tz (0: the
-    // tuned or default depth).
+    // depth as for build).
     static size_t table_bytes(const std::vector<lbm3d_solver*>& members, int tz = 0);
     // One step of every member from its buffer of the given parity
     // (relative to build) into the other one, boundary layers included,

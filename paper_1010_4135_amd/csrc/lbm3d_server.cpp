@@ -286,7 +286,8 @@ void lbm3d_server::run()
             const bool fresh = rebuild || plans[mode].ntiles() == 0;
             if (fresh) {
                 const auto tp = Clock::now();
-                err = plans[mode].build(members, stream);
+                // (tile depth from the launch model for this membership)
+                err = plans[mode].build(members, stream, -1);
                 plan_s += secs_since(tp);
                 rebuilds++;
                 plan_ticks[mode] = 0;
