@@ -105,3 +105,24 @@ def test_plan_rejects_bad_arguments(bad):
     with pytest.raises(lbm3d.LbmError) as ei:
         lbm3d.lbm3d_batch_plan(ps, tz=32, cus=cus)
     assert ei.value.code == -1
+
+
+def _depths(tiles):
+    return set(int(d) for d in (tiles[:, 6] - tiles[:, 5]))
+
+
+def test_model_depth_whole_columns_for_a_large_batch_short_chunks_for_a_few():
+    """Without a tuned depth (tz < 0: the launch model), a batch as large as
+    the 64-solve mix gets whole columns (the deepest tiles, no chunk
+    prologues), and a few small solves get short chunks that spread over
+    the compute units; every node is still covered once."""
+    lbm3d = _lib()
+    big = [g for g in inputs.BATCH_GRIDS for _ in range(13)]
+    tiles, _, _ = lbm3d.lbm3d_batch_plan([_params(g) for g in big], tz=-1, cus=256)
+    nzs = {k: g[2] for k, g in enumerate(big)}
+    assert all(int(t[6] - t[5]) == nzs[int(t[0])] for t in tiles)  # whole columns
+    few = [(64, 64, 64), (128, 128, 128)]
+    tiles, _, _ = lbm3d.lbm3d_batch_plan([_params(g) for g in few], tz=-1, cus=256)
+    d = _depths(tiles)
+    assert max(d) <= 32 and max(d) in (16, 32), d
+    _check_partition(tiles, few, 8, max(d))

@@ -648,3 +648,36 @@ def test_tune_cache_on_disk(tmp_path):
     r = subprocess.run([sys.executable, "-c", prog, "read"], env=env, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     assert r.stdout.split() == t.stdout.split()
+
+
+def test_default_launch_shapes_follow_the_launch_model():
+    """A solve that is not tuned starts from the launch model's shape: the
+    z-chunk depth with the lowest cost for rounds of one tile per compute
+    unit, or the untiled kernel when 8-plane chunks would leave more than a
+    quarter of the units idle (values for a 256-CU device; boundary kinds
+    no other test tunes, so no cached shape applies)."""
+    import glob
+    simds = []
+    for f in glob.glob("/sys/class/kfd/kfd/topology/nodes/*/properties"):
+        try:
+            for line in open(f):
+                if line.startswith("simd_count"):
+                    n = int(line.split()[1])
+                    if n > 0:
+                        simds.append(n)
+        except OSError:
+            pass
+    if not simds or simds[0] != 4 * 256:
+        pytest.skip("the expected shapes are those of a 256-CU device (four SIMDs per CU)")
+    lbm3d = _lib()
+    bc = (1, 1, 3, 3, 1, 1)
+    expected = [((256, 128, 128), "fp32_t64", (8, 32)), ((256, 128, 128), "fp64", (4, 64)),
+                ((128, 128, 128), "fp32_t64", (8, 16)), ((128, 128, 128), "fp64", (4, 32)),
+                ((298, 78, 78), "fp32_t64", (8, 16)), ((298, 78, 78), "fp64", (4, 16)),
+                ((96, 64, 64), "fp64", (4, 8)), ((96, 64, 64), "fp32_t64", (0, 1)),
+                ((64, 64, 64), "fp64", (0, 1)), ((32, 32, 32), "fp32", (0, 1))]
+    for grid, prec, shape in expected:
+        s = lbm3d.Solver(inputs.make_params(grid, bc, precision=prec))
+        got = s.get_tile()
+        s.close()
+        assert got == shape, (grid, prec, got, shape)
