@@ -103,3 +103,40 @@ def test_stream_copy_rate_rejects_bad_arguments(nbytes, launches):
     with pytest.raises(lbm3d.LbmError) as ei:
         lbm3d.lbm3d_stream_copy_rate(nbytes, launches)
     assert ei.value.code == -1
+
+
+def test_batch_entry_points_reject_empty_and_null_lists():
+    """An empty membership or a null handle is refused with E_INVAL before
+    any device call, by every batched entry point."""
+    from paper_1010_4135_amd import lbm3d
+    calls = (lambda h, n: lbm3d.lbm3d_batch_step(h, n),
+             lambda h, n: lbm3d.lbm3d_batch_step_noalloc(h, n),
+             lambda h, n: lbm3d.lbm3d_batch_tune(h, 3))
+    for call in calls:
+        for handles, steps in (([], []), ([None], [1]), ([0, 0], [1, 1])):
+            with pytest.raises(lbm3d.LbmError) as ei:
+                call(handles, steps)
+            assert ei.value.code == lbm3d.E_INVAL
+
+
+def test_server_entry_points_reject_bad_arguments():
+    """A null server, no active slots or a zero budget are refused with
+    E_INVAL before any device call."""
+    import ctypes
+
+    from paper_1010_4135_amd import lbm3d
+    for budget, active in ((0, 4), (1 << 30, 0), (1 << 30, -1)):
+        with pytest.raises(lbm3d.LbmError) as ei:
+            lbm3d.lbm3d_server_create(budget, active)
+        assert ei.value.code == lbm3d.E_INVAL
+    null = ctypes.c_void_p()
+    c = inputs.smooth_periodic(1, grid=(16, 8, 8), precision="fp32")
+    for call in (lambda: lbm3d.lbm3d_server_set_tick(null, 8),
+                 lambda: lbm3d.lbm3d_server_submit(null, c.params, c.fields, 4),
+                 lambda: lbm3d.lbm3d_server_poll(null, 1),
+                 lambda: lbm3d.lbm3d_server_wait(null, 1, (8, 8, 16)),
+                 lambda: lbm3d.lbm3d_server_stats(null),
+                 lambda: lbm3d.lbm3d_server_cancel(null, 1)):
+        with pytest.raises(lbm3d.LbmError) as ei:
+            call()
+        assert ei.value.code == lbm3d.E_INVAL
