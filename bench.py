@@ -421,7 +421,7 @@ def main():
                          "are for shape studies: no counter traffic and no CPU baseline are reported for them")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not implemented", file=sys.stderr)
         sys.exit(2)
 

@@ -1,6 +1,6 @@
 // Host-side checks of the lbm3d runtime, built with AddressSanitizer and
-// UndefinedBehaviorSanitizer on the host code.  The kernels are not part of
-// this build: the launch wrappers below stand in for them and report that
+// UndefinedBehaviorSanitizer on the host code.  The kernels are not compiled
+// into this test program: the launch wrappers below stand in for them and report that
 // there is no device, so every path that would launch a kernel takes its
 // error branch.  Exercises parameter validation and layout, the stability
 // analysis and admission, the batched step's work plans, the autotuner's
