@@ -312,8 +312,8 @@ int32_t lbm3d_set_f(lbm3d_t h, const void* host, size_t bytes);
  * E_STATE if a member is not initialised. */
 int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* nsteps);
 
-/* For callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the same
  * step as lbm3d_batch_step, with the same arguments, errors and results
  * (bitwise), that allocates nothing.  Its work tables (the solve table,
  * tile lists, counters, boundary-layer jobs, step counts and health words) go into a
@@ -322,10 +322,12 @@ int32_t lbm3d_batch_step(lbm3d_t* hs, int32_t count, const int64_t* nsteps);
  * with hipMemcpyAsync on the first member's stream, and every step is
  * launched directly (no graph is instantiated).  4 MiB holds the tables of
  * up to about 200,000 tiles (20 B each, plus about 0.5 KB per solve); the
- * 64-solve batch mix here needs about 0.1 MB at the default tile depth.
+ * benchmark's mix of 64 uneven solves needs about 0.1 MB at the default tile depth.
  * E_NOMEM, before any device work, for a batch whose tables exceed it.
  * All calls on one device share the array: calls that overlap on one device
- * (from several threads or streams) race and must be serialised. */
+ * (from several threads or streams) race and must be serialised.  Like
+ * lbm3d_batch_step it waits for the first member's stream before returning,
+ * so it cannot itself be recorded into a stream capture. */
 int32_t lbm3d_batch_step_noalloc(lbm3d_t* hs, int32_t count, const int64_t* nsteps);
 
 /* Work plan of the batched step, computed on the host (no device work): the
