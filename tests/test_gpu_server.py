@@ -92,11 +92,15 @@ def test_continuous_admission_overlaps_running_solves():
     long_case = inputs.riemann_3d(7, grid=(96, 64, 64), precision="fp32_t64")
     short_case = inputs.riemann_3d(8, grid=(32, 32, 32), precision="fp32_t64")
     with lbm3d.Server(8 << 30, 8, tick_steps=8) as srv:
-        t_long = srv.submit(long_case.params, long_case.fields, 3000)
+        # (about 0.4 s of ticks: far longer than the short
+        # solve's admission and its three ticks)
+        t_long = srv.submit(long_case.params, long_case.fields, 6000)
         time.sleep(0.05)
         t_short = srv.submit(short_case.params, short_case.fields, 20)
         rc_s, _, tm_s = srv.wait(t_short, _shape(short_case))
         rc_l, _, tm_l = srv.wait(t_long, _shape(long_case))
+    print(f"[admission] short admitted {tm_s['t_admit']:.3f} s, done {tm_s['t_done']:.3f} s; "
+          f"long admitted {tm_l['t_admit']:.3f} s, done {tm_l['t_done']:.3f} s", flush=True)
     assert rc_s == lbm3d.OK and rc_l == lbm3d.OK
     assert tm_s["t_admit"] < tm_l["t_done"]
     assert tm_s["t_done"] < tm_l["t_done"]
