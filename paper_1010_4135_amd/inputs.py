@@ -268,6 +268,18 @@ def serve_trace(seed: int, count: int = 64, rate: float = 10.0, grids=SERVE_GRID
     return out
 
 
+def fixed_states():
+    """A fixed (rho, ux, uy, uz, p) per face (-x, +x, -y, +y, -z, +z): subsonic
+    states near smooth_periodic's mean, each flowing into or along its face,
+    for cases that hold fixed-state faces on any axis."""
+    return [[1.2, 0.3, 0.0, 0.05, 1.1],
+            [0.9, -0.25, 0.05, 0.0, 0.95],
+            [1.1, 0.0, 0.2, -0.05, 1.0],
+            [0.95, 0.05, -0.15, 0.0, 1.05],
+            [1.05, -0.05, 0.0, 0.25, 0.9],
+            [1.0, 0.0, 0.05, -0.2, 1.1]]
+
+
 def smooth_periodic(seed: int, grid=(24, 20, 16), amp: float = 0.2, precision=FP64, **model) -> Case:
     """Smooth random periodic state (a few low Fourier modes per field);
     used for conservation and symmetry checks."""

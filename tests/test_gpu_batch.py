@@ -39,10 +39,17 @@ def _mix(precision):
         inputs.smooth_periodic(5, grid=(20, 12, 9), precision=precision),
         inputs.shock_bubble(6, grid=(128, 24, 16), precision=precision, mach=2.5, ratio=0.5),
         inputs.riemann_3d(7, grid=(64, 19, 11), precision=precision),
+        _fixed_state_member(precision),
     ]
 
 
-STEPS = [40, 23, 40, 1, 17, 30, 12]
+def _fixed_state_member(precision):
+    c = inputs.smooth_periodic(8, grid=(40, 12, 10), amp=0.3, precision=precision)
+    c.params = dict(c.params, bc=(2, 1, 2, 3, 1, 2), inflow=inputs.fixed_states())
+    return c
+
+
+STEPS = [40, 23, 40, 1, 17, 30, 12, 25]
 
 
 def _alone(case, steps):

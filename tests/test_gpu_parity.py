@@ -97,6 +97,14 @@ def _small_cases():
     c = inputs.smooth_periodic(25, grid=(65, 9, 7), amp=0.3)
     c.params = dict(c.params, bc=(1, 3, 0, 0, 3, 1))
     out.append(("ragged_x_tail1_65x9x7", c, 40))
+    # fixed-state faces on every axis: the x ones formed in the tiles
+    # (ragged and exactly covered x), the y and z layers written at init
+    c = inputs.smooth_periodic(26, grid=(70, 13, 9), amp=0.3)
+    c.params = dict(c.params, bc=(1, 2, 2, 3, 2, 1), inflow=inputs.fixed_states())
+    out.append(("fixed_states_all_axes_70x13x9", c, 40))
+    c = inputs.smooth_periodic(27, grid=(128, 13, 9), amp=0.3)
+    c.params = dict(c.params, bc=(2, 2, 1, 2, 3, 2), inflow=inputs.fixed_states())
+    out.append(("fixed_states_all_axes_128x13x9", c, 40))
     return out
 
 
@@ -338,10 +346,14 @@ def _tile_cases(precision):
         c = inputs.smooth_periodic(seed, grid=grid, amp=0.3, precision=precision)
         c.params = dict(c.params, bc=bc)
         out.append(c)
+    # fixed states on every axis, the +x one past a ragged 2-column tail
+    c = inputs.smooth_periodic(28, grid=(66, 14, 9), amp=0.2, precision=precision)
+    c.params = dict(c.params, bc=(2, 2, 2, 1, 1, 2), inflow=inputs.fixed_states())
+    out.append(c)
     return out
 
 
-@pytest.mark.parametrize("which", range(9))
+@pytest.mark.parametrize("which", range(10))
 @pytest.mark.parametrize("precision", ["fp64", "fp32_t64"])
 def test_results_do_not_depend_on_tile_shape(precision, which):
     """Every launch shape (untiled, and 64 x BY x TZ tiles with ragged edges
